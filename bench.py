@@ -1,0 +1,187 @@
+"""Benchmark of the iFCTN-TC PAM sweep on one MI355X.
+
+A step is one full PAM sweep (every factor block of eq. (updateG), the
+reconstruction and the X step of eq. (updateX), with the stop-test
+reductions) over the msi256 workload: 256x256x31 multispectral-image-shaped
+tensor, planted iFCTN R=6 + Gaussian bumps + noise, 10% uniform sampling,
+rho = 0.1.  Inputs are resident in HBM before the timed region.
+
+Prints one JSON line with sweeps/s, the roofline of the dominant kernel
+(HIP events on the job's stream) and the CPU oracle baseline.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="msi256")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sweeps", type=int, default=0, help="oracle sweeps (0 = auto, ~10-30 s)")
+    return ap.parse_args()
+
+
+def algorithmic_bytes(dims, esz, mask_frac):
+    """Minimum HBM bytes per launch class for one sweep of the fused pipeline.
+
+    contraction (mode k): read X once                      -> nX * esz
+    fused X step (mode 0 of the next sweep, or the final
+    X-step launch): read X, read the 1-bit mask, write the
+    unobserved entries                                      -> nX * (esz + 1/8 + (1-p) esz)
+    """
+    nX = int(np.prod(dims))
+    read = nX * esz
+    upd = nX * (esz + 1.0 / 8.0 + (1.0 - mask_frac) * esz)
+    return nX, read, upd
+
+
+def cpu_baseline(name, seed, sweeps_req):
+    """The FP64 oracle (single thread) on a bounded sample of the workload."""
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    import oracle
+    from paper_2511_16358_amd import workloads as W
+    p = W.problem(name, seed, lambda d, r, G: oracle.reconstruct(G, d))
+    O64 = p.O.astype(np.float64)
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    if ctx:
+        ctx.__enter__()
+    try:
+        X = oracle.initial_x(O64, p.mask)
+        G = {k: v.copy() for k, v in p.G0.items()}
+        t0 = time.perf_counter()
+        X, G, _ = oracle.pam_sweep(X, G, O64, p.mask, p.dims, p.rho)
+        t1 = time.perf_counter()
+        n = sweeps_req or max(1, min(40, int(15.0 / max(t1 - t0, 1e-3))))
+        for _ in range(n - 1):
+            X, G, _ = oracle.pam_sweep(X, G, O64, p.mask, p.dims, p.rho)
+        dt = time.perf_counter() - t0
+    finally:
+        if ctx:
+            ctx.__exit__(None, None, None)
+    return {"value": n / dt, "unit": "sweeps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} PAM sweeps of {name} (same workload, seed {seed}), float64 numpy, "
+                      f"single thread, {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the sweep of one job fits one GPU; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2511_16358_amd import ifctn
+    from paper_2511_16358_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    prec = ifctn.IFCTN_FP64 if args.precision == "fp64" else ifctn.IFCTN_FP32
+    esz = 8 if prec == ifctn.IFCTN_FP64 else 4
+
+    # synthetic input: planted part assembled by the library itself
+    d = W.draw(args.workload, 0)
+    core = ifctn.assemble(d.dims, d.ranks, d.planted, precision=ifctn.IFCTN_FP64).cpu().numpy()
+    p = W.finish(d, core)
+    Oin = p.O.astype(np.float64) if prec == ifctn.IFCTN_FP64 else p.O
+    job = ifctn.Job(Oin, p.mask, p.G0, p.dims, p.ranks, rho=p.rho, precision=prec)
+    stream = torch.cuda.current_stream()
+
+    job.sweep(args.warmup, stats=True)
+    torch.cuda.synchronize()
+
+    # timed region: exactly K sweeps
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    job.sweep(args.steps, stats=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    ms_per_step = gpu_ms / args.steps
+    sweeps_per_s = args.steps / (gpu_ms / 1e3)
+    st = job.sweep(0, stats=True)
+
+    # second pass with per-kernel events (same K) for the roofline
+    job.timing(True)
+    job.sweep(args.steps, stats=False)
+    per = {}
+    for name, kc in (("contract", ifctn.KC_CONTRACT), ("solve", ifctn.KC_SOLVE),
+                     ("update", ifctn.KC_UPDATE), ("gram", ifctn.KC_GRAM)):
+        ms, n = job.timing_query(kc)
+        per[name] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / max(n, 1)}
+    job.timing(False)
+
+    mask_frac = float(p.mask.mean())
+    nX, rd, upd = algorithmic_bytes(p.dims, esz, mask_frac)
+    # contraction launches: N per sweep; the first of each sweep after the
+    # first also carries the previous sweep's X step
+    N = len(p.dims)
+    n_con = per["contract"]["launches"]
+    n_fused = max(0, args.steps - 1)
+    con_bytes = n_con * rd + n_fused * upd
+    dominant = max(per, key=lambda k: per[k]["total_ms"])
+    con_gbs = con_bytes / (per["contract"]["total_ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "achieved": round(con_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(con_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": "k_contract (mode-k contraction, fused X step on mode 0)",
+            "avg_us": round(per["contract"]["avg_us"], 2)}
+
+    Xf = job.x().cpu().numpy().astype(np.float64)
+    rse = float(np.linalg.norm((Xf - p.X_true).ravel()) / np.linalg.norm(p.X_true.astype(np.float64).ravel()))
+    job.close()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(args.workload, 0, args.cpu_sweeps)
+
+    out = {
+        "metric": "PAM sweeps/sec",
+        "value": round(sweeps_per_s, 2),
+        "unit": "sweeps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == ifctn.IFCTN_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {W.DESCRIPTIONS[args.workload]}",
+                   "dims": list(p.dims), "rank": int(p.ranks[0][1]), "rho": p.rho,
+                   "precision": f"{args.precision} streaming, fp64 Gram/Cholesky/factors/reductions",
+                   "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per.items()},
+        "dominant_kernel_class": dominant,
+        "rse_after_timed_sweeps": rse,
+        "objective": st["objective"],
+        "wall_s_timed": round(wall, 4),
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,148 @@
+/*
+ * ifctn.h -- C ABI of the iFCTN tensor-completion hot path for MI355X (gfx950).
+ *
+ * The library solves the iFCTN tensor-completion model (paper: "iFCTN: an
+ * intra-block Fully-Connected Tensor Network Decomposition for Tensor
+ * Completion", arXiv 2511.16358, eq. (iFCTN-TC)) by proximal alternating
+ * minimisation (Algorithm 1): per sweep, every cherry factor G_{k,i} is
+ * updated column by column by the proximal least-squares closed form of
+ * eq. (updateG), in the order k ascending, i ascending, and then the filled
+ * tensor X is updated by eq. (updateX).  All steps run in HIP kernels on the
+ * device; the header uses only plain C types.
+ *
+ * Conventions
+ *  - Modes are 0-based.  Tensors are dense, row-major (the last mode is the
+ *    fastest), element (i_0,...,i_{N-1}) at offset sum_m i_m * prod_{n>m} I_n.
+ *    (The paper numbers modes from 1 and unfolds with mode 1 fastest; the
+ *    method itself does not depend on the storage order.)
+ *  - The rank matrix R is symmetric, R[a][b] = R[b][a] >= 1 for a != b; the
+ *    diagonal is ignored (Def. 2).
+ *  - Cherry factor G_{k,i} (Def. 1, eq. (3)) has shape R[k][i] x I_k.  A
+ *    "packed factor array" holds all N(N-1) factors as float64 in the order k
+ *    ascending, then i ascending (i != k), each one row-major.
+ *  - Pointers named *_dev are device pointers (hipMalloc / torch tensors on
+ *    the GPU); pointers named *_host are host pointers.  The caller keeps
+ *    ownership of every pointer it passes; the library copies what it needs.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Work is enqueued asynchronously on it; calls that return host values
+ *    (statistics, factors) synchronise it.
+ *  - Every call returns an ifctn_status; no exception crosses the boundary.
+ *    On failure ifctn_last_error() gives a message (thread-local).
+ *  - A job is not thread-safe; different jobs are independent.
+ */
+#ifndef IFCTN_H
+#define IFCTN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define IFCTN_MAX_ORDER 5 /* tensor order N: 2..5 */
+#define IFCTN_MAX_RANK 8  /* every R[a][b] in 1..8 */
+
+typedef enum {
+  IFCTN_OK = 0,
+  IFCTN_E_INVAL = -1,       /* invalid argument (shape, rank, rho, pointer, ...)      */
+  IFCTN_E_NOMEM = -2,       /* device allocation failed                                */
+  IFCTN_E_HIP = -3,         /* HIP runtime error (message kept)                        */
+  IFCTN_E_STATE = -4,       /* call not valid in the job's state                       */
+  IFCTN_E_UNSUPPORTED = -5  /* valid in the paper's model, not supported by this build */
+} ifctn_status;
+
+typedef enum {
+  IFCTN_FP32 = 0,        /* X and the streaming passes in float32; Gram, Cholesky,
+                            factors and reductions in float64                      */
+  IFCTN_BF16_REFINE = 1, /* reserved: bfloat16 streaming passes + float32 refinement */
+  IFCTN_FP64 = 2         /* every step in float64                                   */
+} ifctn_precision;
+
+typedef struct {
+  int32_t order;                                    /* N                               */
+  int64_t dims[IFCTN_MAX_ORDER];                    /* I_0 .. I_{N-1}, each >= 1       */
+  int32_t ranks[IFCTN_MAX_ORDER][IFCTN_MAX_ORDER];  /* symmetric iFCTN ranks           */
+  double rho;    /* proximal weight of the factor blocks, > 0 (Sec. 4.2; 0.1 in Sec. 5) */
+  double rho_x;  /* proximal weight of the X step, > 0 (eq. (updateX)); 0 => rho      */
+  int32_t precision;     /* ifctn_precision                                          */
+  int32_t refine_sweeps; /* reserved, must be 0                                      */
+} ifctn_params;
+
+typedef struct {
+  double rel_change;  /* ||X^{s+1} - X^s||_F / ||X^s||_F of the last sweep (Algorithm 1 stop test) */
+  double objective;   /* F = f(G^{s+1}, X^{s+1}) = 1/2 ||X^{s+1} - iFCTN(G^{s+1})||_F^2 (eq. (iFCTN-TC)) */
+  double x_norm2;     /* ||X^s||_F^2                                                  */
+  double dx_norm2;    /* ||X^{s+1} - X^s||_F^2                                         */
+  double dg_norm2;    /* sum over blocks of ||G_{k,i}^{s+1} - G_{k,i}^s||_F^2 (Lemma 2)  */
+  int32_t sweeps_done;/* sweeps run on this job since ifctn_init                         */
+  int32_t converged;  /* 1 if the last sweep met rel_change < eps (ifctn_complete only)  */
+} ifctn_stats;
+
+typedef struct ifctn_job ifctn_job;
+
+/* Number of float64 entries of a packed factor array: sum over k and i != k of
+ * R[k][i] * I_k (the storage count of Sec. 4.3).  Returns 0 for invalid params. */
+size_t ifctn_num_factor_entries(const ifctn_params* params);
+
+/* Device bytes a job with these params allocates (for admission by HBM
+ * budget).  Returns 0 for invalid params. */
+size_t ifctn_workspace_bytes(const ifctn_params* params);
+
+/* Create a job: validates params, allocates device memory, sets
+ * X^0 = P_Omega(O) (O on Omega, 0 elsewhere; Algorithm 1 initialisation)
+ * and G^0 from G0_host.
+ *   O_dev:    observed tensor, prod(dims) elements, float32 (FP32 precision) or
+ *             float64 (FP64 precision).  Entries off Omega are ignored.
+ *   mask_dev: prod(dims) bytes, nonzero = observed (the sample set Omega).
+ *   G0_host:  packed initial factors (float64), required (Algorithm 1 leaves
+ *             G^0 to the caller).
+ * Fails with IFCTN_E_INVAL when an observed entry is not finite.  Synchronises
+ * the stream.  On success *out owns all device memory until ifctn_destroy. */
+ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
+                        const double* G0_host, void* stream, ifctn_job** out);
+
+/* Run nsweeps >= 0 full PAM sweeps (every factor block by eq. (updateG), then
+ * eq. (updateX)).  Asynchronous when stats is NULL; otherwise synchronises
+ * and fills *stats for the last sweep run. */
+ifctn_status ifctn_sweep(ifctn_job* job, int32_t nsweeps, ifctn_stats* stats);
+
+/* Write a dense tensor to out_dev (float32 for FP32 jobs, float64 for FP64):
+ * which = 0: iFCTN(G) of the current factors (eq. (iFCTN)); which = 1: X. */
+ifctn_status ifctn_reconstruct(ifctn_job* job, void* out_dev, int32_t which);
+
+/* Copy the current factors to a packed float64 host array.  Synchronises. */
+ifctn_status ifctn_get_factors(ifctn_job* job, double* G_host);
+
+/* Release a job and its device memory (NULL is accepted). */
+ifctn_status ifctn_destroy(ifctn_job* job);
+
+/* Algorithm 1 end to end: init, sweeps until rel_change < eps or t_max sweeps
+ * (eps = 0 runs exactly t_max), write X to X_out_dev (same dtype as O_dev),
+ * fill *stats (nullable), destroy.  Synchronises. */
+ifctn_status ifctn_complete(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
+                            const double* G0_host, int32_t t_max, double eps, void* X_out_dev,
+                            ifctn_stats* stats, void* stream);
+
+/* Materialise iFCTN(G) (eq. (iFCTN)) for packed factors G_host into out_dev
+ * (float32 for FP32 params, float64 for FP64), without a job.  Synchronises. */
+ifctn_status ifctn_assemble(const ifctn_params* params, const double* G_host, void* out_dev,
+                            void* stream);
+
+/* Per-kernel timing with HIP events recorded on the job's stream around every
+ * launch of the given kernel class (0 = mode-k contraction, 1 = factor-block
+ * solve, 2 = X update, 3 = Gram weights).  enable = 1 starts a fresh tally, 0 stops.  The query
+ * synchronises and returns the total milliseconds and launch count since the
+ * tally started. */
+ifctn_status ifctn_timing_enable(ifctn_job* job, int32_t enable);
+ifctn_status ifctn_timing_query(ifctn_job* job, int32_t kernel_class, double* total_ms,
+                                int64_t* launches);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char* ifctn_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IFCTN_H */

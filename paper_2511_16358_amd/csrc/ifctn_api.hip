@@ -1,0 +1,822 @@
+// Host side of the iFCTN-TC library: the C ABI of include/ifctn.h, job state,
+// work plans for the kernels and the order of the PAM sweep (Algorithm 1 of
+// arXiv 2511.16358: factor blocks k ascending, i ascending, then the X step).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "ifctn.h"
+#include "ifctn_internal.h"
+
+using namespace ifctn;
+
+namespace {
+
+thread_local std::string g_err;
+
+ifctn_status fail(ifctn_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPTRY(expr)                                                                        \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return fail(e_ == hipErrorOutOfMemory ? IFCTN_E_NOMEM : IFCTN_E_HIP, "%s: %s (%s:%d)", \
+                  #expr, hipGetErrorString(e_), __FILE__, __LINE__);                        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// geometry
+// ---------------------------------------------------------------------------
+struct Geo {
+  int N = 0;
+  int dims[MAXN] = {};
+  long long strides[MAXN] = {};
+  long long nX = 0;
+  int R[MAXN][MAXN] = {};
+  int dtype = 0;       // 0 float32, 1 float64
+  size_t esz = 4;
+  double rho = 0.1, rho_x = 0.1;
+  long long goff[MAXN][MAXN] = {};
+  long long nG = 0;
+  int eid[MAXN][MAXN] = {};
+  int ne = 0;
+  int ea[10] = {}, eb[10] = {};
+  long long woff[10] = {};
+  long long nW = 0;
+};
+
+ifctn_status make_geo(const ifctn_params* p, Geo* g) {
+  if (!p) return fail(IFCTN_E_INVAL, "params is NULL");
+  const int N = p->order;
+  if (N < 2 || N > IFCTN_MAX_ORDER) return fail(IFCTN_E_INVAL, "order %d outside 2..%d", N, IFCTN_MAX_ORDER);
+  if (!(p->rho > 0.0) || !std::isfinite(p->rho)) return fail(IFCTN_E_INVAL, "rho must be > 0");
+  if (p->rho_x < 0.0 || !std::isfinite(p->rho_x)) return fail(IFCTN_E_INVAL, "rho_x must be >= 0 (0 = rho)");
+  if (p->precision == IFCTN_BF16_REFINE) return fail(IFCTN_E_UNSUPPORTED, "BF16_REFINE precision is not built");
+  if (p->precision != IFCTN_FP32 && p->precision != IFCTN_FP64)
+    return fail(IFCTN_E_INVAL, "unknown precision %d", p->precision);
+  if (p->refine_sweeps != 0) return fail(IFCTN_E_INVAL, "refine_sweeps must be 0");
+  g->N = N;
+  long long nX = 1;
+  for (int m = 0; m < N; ++m) {
+    if (p->dims[m] < 1) return fail(IFCTN_E_INVAL, "dims[%d] = %lld < 1", m, (long long)p->dims[m]);
+    if (p->dims[m] > (1LL << 30)) return fail(IFCTN_E_INVAL, "dims[%d] too large", m);
+    if (nX > (1LL << 40) / p->dims[m]) return fail(IFCTN_E_INVAL, "tensor has too many entries");
+    nX *= p->dims[m];
+    g->dims[m] = (int)p->dims[m];
+  }
+  g->nX = nX;
+  long long st = 1;
+  for (int m = N - 1; m >= 0; --m) {
+    g->strides[m] = st;
+    st *= g->dims[m];
+  }
+  for (int a = 0; a < N; ++a)
+    for (int b = 0; b < N; ++b) {
+      if (a == b) continue;
+      const int r = p->ranks[a][b];
+      if (r != p->ranks[b][a]) return fail(IFCTN_E_INVAL, "rank matrix not symmetric at (%d,%d)", a, b);
+      if (r < 1) return fail(IFCTN_E_INVAL, "rank R[%d][%d] = %d < 1", a, b, r);
+      if (r > IFCTN_MAX_RANK) return fail(IFCTN_E_UNSUPPORTED, "rank %d > %d", r, IFCTN_MAX_RANK);
+      g->R[a][b] = r;
+    }
+  g->dtype = p->precision == IFCTN_FP64 ? 1 : 0;
+  g->esz = g->dtype ? 8 : 4;
+  g->rho = p->rho;
+  g->rho_x = p->rho_x > 0.0 ? p->rho_x : p->rho;
+  long long off = 0;
+  for (int k = 0; k < N; ++k)
+    for (int i = 0; i < N; ++i) {
+      if (i == k) continue;
+      g->goff[k][i] = off;
+      off += (long long)g->R[k][i] * g->dims[k];
+    }
+  g->nG = off;
+  off = 0;
+  int e = 0;
+  for (int a = 0; a < N; ++a)
+    for (int b = a + 1; b < N; ++b) {
+      g->eid[a][b] = g->eid[b][a] = e;
+      g->ea[e] = a;
+      g->eb[e] = b;
+      g->woff[e] = off;
+      off += (long long)g->dims[a] * g->dims[b];
+      ++e;
+    }
+  g->ne = e;
+  g->nW = off;
+  return IFCTN_OK;
+}
+
+// W(i_a, i_b) for an ordered pair of modes
+EdgeRef edge_ref(const Geo& g, int a, int b) {
+  EdgeRef r;
+  if (a < b) {
+    r.off = g.woff[g.eid[a][b]];
+    r.s1 = g.dims[b];
+    r.s2 = 1;
+  } else {
+    r.off = g.woff[g.eid[b][a]];
+    r.s1 = 1;
+    r.s2 = g.dims[a];
+  }
+  return r;
+}
+
+long long cdiv(long long a, long long b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// work plans
+// ---------------------------------------------------------------------------
+struct ContractPlan {
+  ContractArgs a;
+  int spt;
+  size_t smem;
+};
+
+constexpr int kTargetBlocks = 1024;
+
+constexpr size_t kMaxLds = 64 << 10;
+
+ContractPlan plan_contract(const Geo& g, int k) {
+  ContractPlan P;
+  ContractArgs& a = P.a;
+  std::memset(&a, 0, sizeof(a));
+  const int N = g.N;
+  // fibre mode f: the contiguous last mode when it is long enough, otherwise
+  // the longest mode != k (the Kronecker accumulation costs Rprod / I_f per element)
+  int f = -1;
+  if (k != N - 1 && g.dims[N - 1] >= 16) {
+    f = N - 1;
+  } else {
+    for (int m = 0; m < N; ++m)
+      if (m != k && (f < 0 || g.dims[m] >= g.dims[f])) f = m;
+  }
+  a.k = k;
+  a.f = f;
+  a.Ik = g.dims[k];
+  a.If = g.dims[f];
+  a.LDF = (a.If % 2 == 0) ? a.If + 1 : a.If;
+  a.stride_k = g.strides[k];
+  a.stride_f = g.strides[f];
+  int cm[MAXC], nc = 0;
+  for (int m = 0; m < N; ++m)
+    if (m != k && m != f) cm[nc++] = m;
+  a.nc = nc;
+  // canonical U column strides over the modes != k (ascending, row-major)
+  long long ust[MAXN];
+  {
+    long long s = 1;
+    for (int m = N - 1; m >= 0; --m) {
+      if (m == k) continue;
+      ust[m] = s;
+      s *= g.R[k][m];
+    }
+  }
+  a.Rf = g.R[f][k];
+  a.ustf = ust[f];
+  a.Rc = 1;
+  for (int c = 0; c < nc; ++c) {
+    const int m = cm[c];
+    a.cdim[c] = g.dims[m];
+    a.cstride[c] = g.strides[m];
+    a.crank[c] = g.R[m][k];
+    a.gcoff[c] = g.goff[m][k];
+    a.ecf[c] = edge_ref(g, m, f);
+    a.ustc[c] = ust[m];
+    a.Rc *= a.crank[c];
+    if (k == 0) a.e0c[c] = edge_ref(g, 0, m);
+  }
+  a.gfoff = g.goff[f][k];
+  a.Rprod = a.Rc * a.Rf;
+  a.ncc = 0;
+  for (int x = 0; x < nc; ++x)
+    for (int y = x + 1; y < nc; ++y) {
+      a.cc_a[a.ncc] = x;
+      a.cc_b[a.ncc] = y;
+      a.ecc[a.ncc] = edge_ref(g, cm[x], cm[y]);
+      ++a.ncc;
+    }
+  if (k == 0) a.e0f = edge_ref(g, 0, f);
+  a.rho_x = g.rho_x;
+  a.nplanes = g.nX / ((long long)a.Ik * a.If);
+  // enumeration order: axes by decreasing memory stride (j, plane, fibre)
+  long long st[3] = {a.stride_k, nc > 0 ? a.cstride[nc - 1] : (long long)1 << 62, a.stride_f};
+  int ord[3] = {0, 1, 2};
+  std::sort(ord, ord + 3, [&](int x, int y) { return st[x] > st[y]; });
+  for (int t = 0; t < 3; ++t) a.ord[t] = ord[t];
+  int jpos = 0;
+  for (int t = 0; t < 3; ++t)
+    if (ord[t] == 0) jpos = t;
+
+  // tiling: an LDS tile of at most `tile` streaming elements, at most 32
+  // float64 accumulators per thread, split partials bounded by a quarter of X
+  const long long tile = g.dtype ? 4096 : 8192;
+  const long long budget = std::max<long long>(g.nX * (long long)g.esz / 4, 256 << 10);
+  const long long smax = std::max<long long>(1, budget / ((long long)a.Ik * a.Rprod * 8));
+  const long long jcap = std::max<long long>(1, std::min<long long>((long long)NT * 32 / a.Rprod, tile / a.LDF));
+  long long JT, S;
+  if (jpos == 0) {
+    // j is the slowest axis: one j per workgroup streams contiguous slices
+    JT = a.Ik;
+    S = std::max<long long>(1, std::min<long long>(std::min(smax, a.nplanes), cdiv(kTargetBlocks, JT)));
+  } else {
+    S = std::max<long long>(1, std::min(smax, a.nplanes));
+    const long long jt_min = cdiv(a.Ik, jcap);
+    long long jt_max = a.Ik;
+    // j innermost: keep runs of at least 16 consecutive elements
+    if (jpos == 2) jt_max = std::max<long long>(jt_min, cdiv(a.Ik, std::min<long long>(a.Ik, 16)));
+    JT = std::min(jt_max, std::max(jt_min, cdiv(kTargetBlocks, S)));
+  }
+  long long jn = cdiv(a.Ik, JT);
+  jn = std::min(jn, jcap);
+  JT = cdiv(a.Ik, jn);
+  const long long PPW = cdiv(a.nplanes, S);
+  S = cdiv(a.nplanes, PPW);
+  long long PB = std::max<long long>(1, std::min<long long>({tile / (jn * a.LDF), 256, PPW}));
+  a.jn = (int)jn;
+  a.JT = (int)JT;
+  a.S = (int)S;
+  a.PPW = PPW;
+  a.PB = (int)PB;
+  // shrink the plane batch until the LDS layout fits
+  while (a.PB > 1 && contract_smem_bytes(g.dtype, a) > kMaxLds) a.PB = std::max(1, a.PB * 3 / 4);
+  const long long slots = jn * a.Rprod;
+  int spt = 1;
+  while ((long long)spt * NT < slots) spt *= 2;
+  P.spt = spt;
+  P.smem = contract_smem_bytes(g.dtype, a);
+  return P;
+}
+
+
+// Invariants every launch relies on (indices stay inside X, the LDS layout
+// and the partial buffers).  A plan that breaks one is rejected before any
+// kernel runs.
+bool plan_ok(const Geo& g, const ContractPlan& P, const char** why) {
+  const ContractArgs& a = P.a;
+  if ((long long)a.JT * a.jn < a.Ik || (long long)(a.JT - 1) * a.jn >= a.Ik) { *why = "j tiling"; return false; }
+  if ((long long)a.S * a.PPW < a.nplanes || (long long)(a.S - 1) * a.PPW >= a.nplanes) { *why = "plane split"; return false; }
+  if ((long long)a.nplanes * a.Ik * a.If != g.nX) { *why = "plane count"; return false; }
+  if ((long long)a.jn * a.Rprod > (long long)P.spt * NT || P.spt > 32) { *why = "accumulator slots"; return false; }
+  if (a.PB < 1 || a.PB > 256 || a.jn < 1) { *why = "batch"; return false; }
+  if (P.smem > kMaxLds) { *why = "LDS size"; return false; }
+  if (a.Rf > MAXR || a.Rc > 4096) { *why = "rank product"; return false; }
+  return true;
+}
+
+QArgs plan_q(const Geo& g, int k, long long* qsize) {
+  QArgs a;
+  std::memset(&a, 0, sizeof(a));
+  const int N = g.N;
+  a.ni = N - 1;
+  a.nd = N - 2;
+  a.ndd = (N - 2) * (N - 3) / 2;
+  long long blk = 0, qo = 0;
+  int t = 0;
+  for (int i = 0; i < N; ++i) {
+    if (i == k) continue;
+    a.Ii[t] = g.dims[i];
+    a.R[t] = g.R[k][i];
+    a.np[t] = a.R[t] * (a.R[t] + 1) / 2;
+    int dm[MAXC], nd = 0;
+    long long D = 1;
+    for (int m = 0; m < N; ++m)
+      if (m != k && m != i) dm[nd++] = m;
+    for (int c = 0; c < nd; ++c) {
+      a.ddim[t][c] = g.dims[dm[c]];
+      a.edi[t][c] = edge_ref(g, dm[c], i);
+      D *= g.dims[dm[c]];
+    }
+    int q = 0;
+    for (int x = 0; x < nd; ++x)
+      for (int y = x + 1; y < nd; ++y) {
+        a.dd_a[t][q] = x;
+        a.dd_b[t][q] = y;
+        a.edd[t][q] = edge_ref(g, dm[x], dm[y]);
+        ++q;
+      }
+    a.D[t] = D;
+    int lanes = (int)std::min<long long>(64, cdiv(a.Ii[t], 8));
+    int lg = 0;
+    while ((1 << lg) < lanes) ++lg;
+    a.lg2P[t] = lg;
+    a.CH[t] = (int)cdiv(a.Ii[t], 1 << lg);
+    a.blk0[t] = blk;
+    blk += cdiv(D << lg, NT);
+    a.qoff[t] = qo;
+    qo += D * a.np[t];
+    a.gik[t] = g.goff[i][k];
+    ++t;
+  }
+  a.blk0[t] = blk;
+  *qsize = qo;
+  return a;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// job
+// ---------------------------------------------------------------------------
+struct ifctn_job {
+  Geo g;
+  hipStream_t stream = nullptr;
+  unsigned char* arena = nullptr;
+  size_t arena_bytes = 0;
+  void* X = nullptr;
+  uint32_t* bits = nullptr;
+  double* G = nullptr;
+  double* W64 = nullptr;
+  void* Wc = nullptr;
+  double* Q = nullptr;
+  double* Upart = nullptr;
+  double* Ufin = nullptr;
+  double* normpart = nullptr;
+  double* dgpart = nullptr;
+  double* stats5 = nullptr;
+  int* flag = nullptr;
+  ContractPlan cplan[MAXN];
+  QArgs qplan[MAXN];
+  SolveArgs splan[MAXN][MAXN];
+  int nnorm = 0, ndg = 0;
+  bool pending = false;
+  int sweeps_done = 0;
+  bool timing = false;
+  std::vector<hipEvent_t> ev[KC_COUNT];
+  size_t evn[KC_COUNT] = {0, 0, 0, 0};
+};
+
+namespace {
+
+struct Sizes {
+  size_t x, bits, G, W64, Wc, Q, Upart, Ufin, normpart, dgpart, stats, flag, total;
+};
+
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
+  Sizes s;
+  s.x = al256(g.nX * g.esz);
+  s.bits = al256(((g.nX + 63) / 64) * 8);
+  s.G = al256(g.nG * 8);
+  s.W64 = al256(g.nW * 8);
+  s.Wc = al256(g.nW * g.esz);
+  long long qmax = 0, upmax = 0, ufmax = 0, nnorm = 0, ndg = 0;
+  const bool dbg = std::getenv("IFCTN_DEBUG_PLAN") != nullptr;
+  for (int k = 0; k < g.N; ++k) {
+    ContractPlan P = plan_contract(g, k);
+    long long qs = 0;
+    QArgs Q = plan_q(g, k, &qs);
+    if (dbg) {
+      const ContractArgs& a = P.a;
+      std::fprintf(stderr,
+                   "[ifctn plan] k=%d f=%d ord=%d%d%d Ik=%d If=%d LDF=%d nc=%d Rf=%d Rc=%d Rprod=%d jn=%d JT=%d S=%d "
+                   "PPW=%lld PB=%d nplanes=%lld spt=%d smem=%zu blocks=%lld upart=%lld | Q blocks=%lld size=%lld\n",
+                   k, a.f, a.ord[0], a.ord[1], a.ord[2], a.Ik, a.If, a.LDF, a.nc, a.Rf, a.Rc, a.Rprod, a.jn, a.JT, a.S, a.PPW, a.PB,
+                   a.nplanes, P.spt, P.smem, (long long)a.JT * a.S, (long long)a.S * a.Ik * a.Rprod,
+                   Q.blk0[Q.ni], qs);
+    }
+    if (cp) cp[k] = P;
+    if (qp) qp[k] = Q;
+    qmax = std::max(qmax, qs);
+    upmax = std::max(upmax, (long long)P.a.S * P.a.Ik * P.a.Rprod);
+    ufmax = std::max(ufmax, (long long)P.a.Ik * P.a.Rprod);
+    if (k == 0) nnorm = (long long)P.a.JT * P.a.S;
+    ndg += (long long)(g.N - 1) * g.dims[k];
+  }
+  s.Q = al256(qmax * 8);
+  s.Upart = al256(upmax * 8);
+  s.Ufin = al256(ufmax * 8);
+  s.normpart = al256(nnorm * 3 * 8);
+  s.dgpart = al256(ndg * 8);
+  s.stats = al256(8 * 8);
+  s.flag = al256(16);
+  s.total = s.x + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.normpart + s.dgpart + s.stats + s.flag;
+  return s;
+}
+
+void build_solve_plans(ifctn_job* J) {
+  const Geo& g = J->g;
+  const int N = g.N;
+  long long dgo = 0;
+  for (int k = 0; k < N; ++k) {
+    const ContractPlan& P = J->cplan[k];
+    const QArgs& Q = J->qplan[k];
+    int umodes[MAXN - 1], nu = 0;
+    for (int m = 0; m < N; ++m)
+      if (m != k) umodes[nu++] = m;
+    long long ust[MAXN - 1];
+    long long s = 1;
+    for (int t = nu - 1; t >= 0; --t) {
+      ust[t] = s;
+      s *= g.R[k][umodes[t]];
+    }
+    int t = 0;
+    bool first = true;
+    for (int i = 0; i < N; ++i) {
+      if (i == k) continue;
+      SolveArgs a;
+      std::memset(&a, 0, sizeof(a));
+      a.k = k;
+      a.i = i;
+      a.Ik = g.dims[k];
+      a.Ii = g.dims[i];
+      a.R = g.R[k][i];
+      a.np = a.R * (a.R + 1) / 2;
+      a.rho = g.rho;
+      int dm[MAXC], nd = 0;
+      for (int m = 0; m < N; ++m)
+        if (m != k && m != i) dm[nd++] = m;
+      a.nd = nd;
+      a.D = Q.D[t];
+      for (int c = 0; c < nd; ++c) {
+        a.ddim[c] = g.dims[dm[c]];
+        a.ekd[c] = edge_ref(g, k, dm[c]);
+      }
+      a.Q = J->Q + Q.qoff[t];
+      a.Rprod = P.a.Rprod;
+      a.nu = nu;
+      for (int u = 0; u < nu; ++u) {
+        a.urank[u] = g.R[k][umodes[u]];
+        a.ustride[u] = ust[u];
+        a.ugoff[u] = g.goff[k][umodes[u]];
+        if (umodes[u] == i) a.upos_i = u;
+      }
+      a.first = first ? 1 : 0;
+      a.S = P.a.S;
+      a.Upart = J->Upart;
+      a.Ufin = J->Ufin;
+      a.goff_ki = g.goff[k][i];
+      a.goff_ik = g.goff[i][k];
+      const EdgeRef w = edge_ref(g, k, i);
+      a.w_off = w.off;
+      a.w_sj = w.s1;
+      a.w_sy = w.s2;
+      a.W64 = J->W64;
+      a.Wc = J->Wc;
+      a.G = J->G;
+      a.dgpart = J->dgpart + dgo;
+      dgo += a.Ik;
+      J->splan[k][i] = a;
+      first = false;
+      ++t;
+    }
+  }
+  J->ndg = (int)dgo;
+}
+
+hipError_t timed(ifctn_job* J, int cls, hipError_t (*fn)(ifctn_job*, const void*), const void* ctx) {
+  if (!J->timing) return fn(J, ctx);
+  auto& v = J->ev[cls];
+  size_t n = J->evn[cls];
+  while (v.size() < 2 * (n + 1)) {
+    hipEvent_t e;
+    hipError_t err = hipEventCreate(&e);
+    if (err != hipSuccess) return err;
+    v.push_back(e);
+  }
+  hipError_t err = hipEventRecord(v[2 * n], J->stream);
+  if (err != hipSuccess) return err;
+  err = fn(J, ctx);
+  if (err != hipSuccess) return err;
+  err = hipEventRecord(v[2 * n + 1], J->stream);
+  J->evn[cls] = n + 1;
+  return err;
+}
+
+struct ContractCall {
+  int k;
+  bool upd, con;
+};
+
+hipError_t do_contract(ifctn_job* J, const void* c) {
+  const ContractCall* cc = (const ContractCall*)c;
+  const ContractPlan& P = J->cplan[cc->k];
+  return launch_contract(J->g.dtype, cc->upd, cc->con, cc->con ? P.spt : 1, P.a, P.smem, J->stream);
+}
+
+hipError_t do_gram(ifctn_job* J, const void* c) { return launch_q(*(const QArgs*)c, J->stream); }
+
+hipError_t do_solve(ifctn_job* J, const void* c) {
+  const SolveArgs* a = (const SolveArgs*)c;
+  return launch_solve(J->g.dtype, *a, J->stream);
+}
+
+hipError_t run_sweep(ifctn_job* J) {
+  const int N = J->g.N;
+  hipError_t e;
+  for (int k = 0; k < N; ++k) {
+    e = timed(J, KC_GRAM, do_gram, &J->qplan[k]);
+    if (e != hipSuccess) return e;
+    ContractCall cc{k, k == 0 && J->pending, true};
+    e = timed(J, KC_CONTRACT, do_contract, &cc);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < N; ++i) {
+      if (i == k) continue;
+      e = timed(J, KC_SOLVE, do_solve, &J->splan[k][i]);
+      if (e != hipSuccess) return e;
+    }
+  }
+  J->pending = true;
+  J->sweeps_done++;
+  return hipSuccess;
+}
+
+hipError_t flush_update(ifctn_job* J) {
+  if (!J->pending) return hipSuccess;
+  ContractCall cc{0, true, false};
+  hipError_t e = timed(J, KC_UPDATE, do_contract, &cc);
+  J->pending = false;
+  return e;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+const char* ifctn_last_error(void) { return g_err.c_str(); }
+
+size_t ifctn_num_factor_entries(const ifctn_params* params) {
+  Geo g;
+  if (make_geo(params, &g) != IFCTN_OK) return 0;
+  return (size_t)g.nG;
+}
+
+size_t ifctn_workspace_bytes(const ifctn_params* params) {
+  Geo g;
+  if (make_geo(params, &g) != IFCTN_OK) return 0;
+  ContractPlan cp[MAXN];
+  const Sizes s = job_sizes(g, cp, nullptr);
+  const char* why = "";
+  for (int k = 0; k < g.N; ++k)
+    if (!plan_ok(g, cp[k], &why)) {
+      fail(IFCTN_E_UNSUPPORTED, "no valid work plan for mode %d (%s)", k, why);
+      return 0;
+    }
+  return s.total;
+}
+
+ifctn_status ifctn_destroy(ifctn_job* job) {
+  if (!job) return IFCTN_OK;
+  for (int c = 0; c < KC_COUNT; ++c)
+    for (hipEvent_t e : job->ev[c]) (void)hipEventDestroy(e);
+  if (job->arena) (void)hipFree(job->arena);
+  delete job;
+  return IFCTN_OK;
+}
+
+ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
+                        const double* G0_host, void* stream, ifctn_job** out) {
+  if (!out) return fail(IFCTN_E_INVAL, "out is NULL");
+  *out = nullptr;
+  Geo g;
+  ifctn_status st = make_geo(params, &g);
+  if (st != IFCTN_OK) return st;
+  if (!O_dev || !mask_dev) return fail(IFCTN_E_INVAL, "O_dev and mask_dev are required");
+  if (!G0_host) return fail(IFCTN_E_INVAL, "G0_host (initial factors) is required");
+  ifctn_job* J = new ifctn_job();
+  J->g = g;
+  J->stream = (hipStream_t)stream;
+  const Sizes s = job_sizes(g, J->cplan, J->qplan);
+  for (int k = 0; k < g.N; ++k) {
+    const char* why = "";
+    if (!plan_ok(g, J->cplan[k], &why)) {
+      delete J;
+      return fail(IFCTN_E_UNSUPPORTED, "no valid work plan for mode %d (%s)", k, why);
+    }
+  }
+  hipError_t e = hipMalloc((void**)&J->arena, s.total);
+  if (e != hipSuccess) {
+    delete J;
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? IFCTN_E_NOMEM : IFCTN_E_HIP, "hipMalloc(%zu): %s", s.total,
+                hipGetErrorString(e));
+  }
+  J->arena_bytes = s.total;
+  unsigned char* p = J->arena;
+  J->X = p;                      p += s.x;
+  J->bits = (uint32_t*)p;        p += s.bits;
+  J->G = (double*)p;             p += s.G;
+  J->W64 = (double*)p;           p += s.W64;
+  J->Wc = p;                     p += s.Wc;
+  J->Q = (double*)p;             p += s.Q;
+  J->Upart = (double*)p;         p += s.Upart;
+  J->Ufin = (double*)p;          p += s.Ufin;
+  J->normpart = (double*)p;      p += s.normpart;
+  J->dgpart = (double*)p;        p += s.dgpart;
+  J->stats5 = (double*)p;        p += s.stats;
+  J->flag = (int*)p;             p += s.flag;
+  for (int k = 0; k < g.N; ++k) {
+    ContractArgs& a = J->cplan[k].a;
+    a.X = J->X;
+    a.maskbits = J->bits;
+    a.Wc = J->Wc;
+    a.G = J->G;
+    a.Upart = J->Upart;
+    a.normpart = J->normpart;
+    J->qplan[k].W64 = J->W64;
+    J->qplan[k].G = J->G;
+    J->qplan[k].Q = J->Q;
+  }
+  J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S;
+  build_solve_plans(J);
+  auto bail = [&](ifctn_status code, const char* what, hipError_t err) {
+    ifctn_status r = fail(code, "%s: %s", what, hipGetErrorString(err));
+    ifctn_destroy(J);
+    return r;
+  };
+#define INIT_TRY(expr)                                         \
+  do {                                                         \
+    hipError_t e_ = (expr);                                    \
+    if (e_ != hipSuccess) return bail(IFCTN_E_HIP, #expr, e_); \
+  } while (0)
+  INIT_TRY(hipMemsetAsync(J->normpart, 0, s.normpart, J->stream));
+  INIT_TRY(hipMemsetAsync(J->dgpart, 0, s.dgpart, J->stream));
+  INIT_TRY(hipMemsetAsync(J->flag, 0, s.flag, J->stream));
+  INIT_TRY(hipMemcpyAsync(J->G, G0_host, g.nG * 8, hipMemcpyHostToDevice, J->stream));
+  INIT_TRY(launch_init_x(g.dtype, O_dev, mask_dev, J->X, J->bits, J->flag, g.nX, J->stream));
+  for (int e2 = 0; e2 < g.ne; ++e2) {
+    const int a = g.ea[e2], b = g.eb[e2];
+    INIT_TRY(launch_edge(g.dtype, J->G + g.goff[a][b], J->G + g.goff[b][a], g.R[a][b], g.dims[a], g.dims[b],
+                         J->W64 + g.woff[e2], (unsigned char*)J->Wc + g.woff[e2] * g.esz, J->stream));
+  }
+  int bad = 0;
+  INIT_TRY(hipMemcpyAsync(&bad, J->flag, sizeof(int), hipMemcpyDeviceToHost, J->stream));
+  INIT_TRY(hipStreamSynchronize(J->stream));
+#undef INIT_TRY
+  if (bad) {
+    ifctn_destroy(J);
+    return fail(IFCTN_E_INVAL, "an observed entry of O is not finite");
+  }
+  *out = J;
+  return IFCTN_OK;
+}
+
+ifctn_status ifctn_sweep(ifctn_job* J, int32_t nsweeps, ifctn_stats* stats) {
+  if (!J) return fail(IFCTN_E_INVAL, "job is NULL");
+  if (nsweeps < 0) return fail(IFCTN_E_INVAL, "nsweeps < 0");
+  for (int s = 0; s < nsweeps; ++s) HIPTRY(run_sweep(J));
+  HIPTRY(flush_update(J));
+  if (stats) {
+    HIPTRY(launch_finalize(J->normpart, J->nnorm, J->dgpart, J->ndg, J->stats5, J->stream));
+    double h[5];
+    HIPTRY(hipMemcpyAsync(h, J->stats5, sizeof(h), hipMemcpyDeviceToHost, J->stream));
+    HIPTRY(hipStreamSynchronize(J->stream));
+    stats->dx_norm2 = h[0];
+    stats->x_norm2 = h[1];
+    stats->objective = 0.5 * h[2];
+    stats->dg_norm2 = h[3];
+    stats->rel_change = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] == 0.0 ? 0.0 : INFINITY);
+    stats->sweeps_done = J->sweeps_done;
+    stats->converged = 0;
+  }
+  return IFCTN_OK;
+}
+
+ifctn_status ifctn_reconstruct(ifctn_job* J, void* out_dev, int32_t which) {
+  if (!J || !out_dev) return fail(IFCTN_E_INVAL, "job and out_dev are required");
+  if (which == 1) {
+    HIPTRY(flush_update(J));
+    HIPTRY(hipMemcpyAsync(out_dev, J->X, J->g.nX * J->g.esz, hipMemcpyDeviceToDevice, J->stream));
+    return IFCTN_OK;
+  }
+  if (which != 0) return fail(IFCTN_E_INVAL, "which must be 0 or 1");
+  ReconArgs r;
+  std::memset(&r, 0, sizeof(r));
+  r.N = J->g.N;
+  for (int m = 0; m < r.N; ++m) r.dims[m] = J->g.dims[m];
+  r.nX = J->g.nX;
+  r.ne = J->g.ne;
+  for (int e = 0; e < r.ne; ++e) {
+    r.ea[e] = J->g.ea[e];
+    r.eb[e] = J->g.eb[e];
+    r.woff[e] = J->g.woff[e];
+  }
+  r.Wc = J->Wc;
+  r.out = out_dev;
+  HIPTRY(launch_reconstruct(J->g.dtype, r, J->stream));
+  return IFCTN_OK;
+}
+
+ifctn_status ifctn_get_factors(ifctn_job* J, double* G_host) {
+  if (!J || !G_host) return fail(IFCTN_E_INVAL, "job and G_host are required");
+  HIPTRY(hipMemcpyAsync(G_host, J->G, J->g.nG * 8, hipMemcpyDeviceToHost, J->stream));
+  HIPTRY(hipStreamSynchronize(J->stream));
+  return IFCTN_OK;
+}
+
+ifctn_status ifctn_complete(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
+                            const double* G0_host, int32_t t_max, double eps, void* X_out_dev,
+                            ifctn_stats* stats, void* stream) {
+  if (t_max < 0) return fail(IFCTN_E_INVAL, "t_max < 0");
+  if (!(eps >= 0.0)) return fail(IFCTN_E_INVAL, "eps < 0");
+  if (!X_out_dev) return fail(IFCTN_E_INVAL, "X_out_dev is required");
+  ifctn_job* J = nullptr;
+  ifctn_status st = ifctn_init(params, O_dev, mask_dev, G0_host, stream, &J);
+  if (st != IFCTN_OK) return st;
+  ifctn_stats s;
+  std::memset(&s, 0, sizeof(s));
+  if (eps == 0.0) {
+    st = ifctn_sweep(J, t_max, &s);
+  } else {
+    for (int t = 0; t < t_max; ++t) {
+      st = ifctn_sweep(J, 1, &s);
+      if (st != IFCTN_OK) break;
+      if (s.rel_change < eps) {
+        s.converged = 1;
+        break;
+      }
+    }
+  }
+  if (st == IFCTN_OK) st = ifctn_reconstruct(J, X_out_dev, 1);
+  if (st == IFCTN_OK) {
+    hipError_t e = hipStreamSynchronize(J->stream);
+    if (e != hipSuccess) st = fail(IFCTN_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
+  }
+  if (st == IFCTN_OK && stats) *stats = s;
+  ifctn_destroy(J);
+  return st;
+}
+
+ifctn_status ifctn_assemble(const ifctn_params* params, const double* G_host, void* out_dev, void* stream) {
+  Geo g;
+  ifctn_status st = make_geo(params, &g);
+  if (st != IFCTN_OK) return st;
+  if (!G_host || !out_dev) return fail(IFCTN_E_INVAL, "G_host and out_dev are required");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bG = al256(g.nG * 8), bW = al256(g.nW * 8), bWc = al256(g.nW * g.esz);
+  unsigned char* buf = nullptr;
+  HIPTRY(hipMalloc((void**)&buf, bG + bW + bWc));
+  double* G = (double*)buf;
+  double* W64 = (double*)(buf + bG);
+  unsigned char* Wc = buf + bG + bW;
+  hipError_t e = hipMemcpyAsync(G, G_host, g.nG * 8, hipMemcpyHostToDevice, s);
+  for (int x = 0; x < g.ne && e == hipSuccess; ++x) {
+    const int a = g.ea[x], b = g.eb[x];
+    e = launch_edge(g.dtype, G + g.goff[a][b], G + g.goff[b][a], g.R[a][b], g.dims[a], g.dims[b],
+                    W64 + g.woff[x], Wc + g.woff[x] * g.esz, s);
+  }
+  if (e == hipSuccess) {
+    ReconArgs r;
+    std::memset(&r, 0, sizeof(r));
+    r.N = g.N;
+    for (int m = 0; m < g.N; ++m) r.dims[m] = g.dims[m];
+    r.nX = g.nX;
+    r.ne = g.ne;
+    for (int x = 0; x < g.ne; ++x) {
+      r.ea[x] = g.ea[x];
+      r.eb[x] = g.eb[x];
+      r.woff[x] = g.woff[x];
+    }
+    r.Wc = Wc;
+    r.out = out_dev;
+    e = launch_reconstruct(g.dtype, r, s);
+  }
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(IFCTN_E_HIP, "assemble: %s", hipGetErrorString(e));
+  return IFCTN_OK;
+}
+
+ifctn_status ifctn_timing_enable(ifctn_job* J, int32_t enable) {
+  if (!J) return fail(IFCTN_E_INVAL, "job is NULL");
+  HIPTRY(hipStreamSynchronize(J->stream));
+  J->timing = enable != 0;
+  for (int c = 0; c < KC_COUNT; ++c) J->evn[c] = 0;
+  return IFCTN_OK;
+}
+
+ifctn_status ifctn_timing_query(ifctn_job* J, int32_t kernel_class, double* total_ms, int64_t* launches) {
+  if (!J || !total_ms || !launches) return fail(IFCTN_E_INVAL, "job, total_ms and launches are required");
+  if (kernel_class < 0 || kernel_class >= KC_COUNT) return fail(IFCTN_E_INVAL, "unknown kernel class");
+  HIPTRY(hipStreamSynchronize(J->stream));
+  double t = 0.0;
+  for (size_t n = 0; n < J->evn[kernel_class]; ++n) {
+    float ms = 0.f;
+    HIPTRY(hipEventElapsedTime(&ms, J->ev[kernel_class][2 * n], J->ev[kernel_class][2 * n + 1]));
+    t += ms;
+  }
+  *total_ms = t;
+  *launches = (int64_t)J->evn[kernel_class];
+  return IFCTN_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal declarations shared by the HIP kernels and the host orchestration
+// of the iFCTN-TC library.  Not part of the public ABI (include/ifctn.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ifctn {
+
+constexpr int MAXN = 5;              // tensor order
+constexpr int MAXR = 8;              // edge rank
+constexpr int MAXC = MAXN - 2;       // modes other than k and the fibre mode
+constexpr int MAXP = MAXR * (MAXR + 1) / 2;  // distinct entries of an R x R Gram matrix
+constexpr int NT = 256;              // threads per workgroup (4 wavefronts of 64)
+
+// Oriented reference to an edge matrix: W(i_first, i_second) lives at
+// base[off + i_first * s1 + i_second * s2].  Edge {a,b}, a < b, is stored
+// row-major I_a x I_b, so the reversed orientation just swaps the strides.
+struct EdgeRef {
+  long long off;
+  int s1, s2;
+};
+
+// Mode-k contraction U_k(j, r_{-k}) = sum_{i_{-k}} X(i) S_k(i_{-k}) prod_{m != k}
+// G_{m,k}(r_m, i_m), organised by "planes": for a fixed index c of the modes
+// other than k and the fibre mode f, the plane is the I_k x I_f slice of X.
+// Optionally fused with the X step of the previous sweep (k == 0).
+struct ContractArgs {
+  int k, f, nc;
+  int Ik, If, LDF;
+  long long stride_k, stride_f;
+  int cdim[MAXC];
+  long long cstride[MAXC];
+  int crank[MAXC];       // R_{m,k} of each c-mode
+  long long gcoff[MAXC]; // offset of G_{m,k} (R_{m,k} x I_m) in the packed factors
+  long long gfoff;       // offset of G_{f,k} (R_{f,k} x I_f)
+  int Rf, Rc, Rprod;
+  EdgeRef ecf[MAXC];     // W(i_m, i_f) for each c-mode m
+  int ncc;               // edges among c-modes
+  int cc_a[3], cc_b[3];
+  EdgeRef ecc[3];
+  long long ustc[MAXC];   // canonical U column stride of each c-mode
+  long long ustf;         // canonical U column stride of the fibre mode
+  // tiling: the X elements of a batch are enumerated over three axes
+  // (0 = j, 1 = plane, 2 = fibre) in the order ord[0] (outer) .. ord[2]
+  // (inner), i.e. by decreasing memory stride, so that consecutive lanes
+  // touch consecutive addresses
+  int ord[3];
+  int jn, PB, JT, S;
+  long long PPW, nplanes;
+  // fused X step (k == 0 only)
+  EdgeRef e0c[MAXC];     // W(i_0, i_m) for the c-modes
+  EdgeRef e0f;           // W(i_0, i_f)
+  double rho_x;
+  // buffers
+  void* X;
+  const uint32_t* maskbits;
+  const void* Wc;        // edge matrices in the streaming precision
+  const double* G;       // packed float64 factors
+  double* Upart;         // [S][I_k][Rprod] split partial sums
+  double* normpart;      // [blocks][3]: ||dX||^2, ||X||^2, ||X_new - Xhat||^2
+};
+
+// Q_{k,i}(d; r, r') = sum_{i_i} S_k(i_{-k})^2 G_{i,k}(r, i_i) G_{i,k}(r', i_i),
+// d = index over the modes other than k and i; constant during block k.
+struct QArgs {
+  int ni;
+  int Ii[MAXN - 1];
+  int R[MAXN - 1];
+  int np[MAXN - 1];
+  long long D[MAXN - 1];
+  int lg2P[MAXN - 1];    // log2 of the lanes per d (power of two <= 64)
+  int CH[MAXN - 1];      // fibre chunk per lane
+  long long blk0[MAXN];  // first workgroup of each i; blk0[ni] = total
+  long long qoff[MAXN - 1];
+  long long gik[MAXN - 1];
+  int nd;
+  int ddim[MAXN - 1][MAXC];
+  EdgeRef edi[MAXN - 1][MAXC];   // W(i_m, i_i), m in d
+  int ndd;
+  int dd_a[MAXN - 1][3], dd_b[MAXN - 1][3];
+  EdgeRef edd[MAXN - 1][3];
+  const double* W64;
+  const double* G;
+  double* Q;
+};
+
+// One factor block G_{k,i}: per column j, H_j = sum_d w_j(d) Q(d) + rho I with
+// w_j(d) = prod_{m in d} W_{k,m}(j, i_m)^2, b_j from U_k, Cholesky solve, then
+// the edge matrix of {k,i} is refreshed for that column.
+struct SolveArgs {
+  int k, i;
+  int Ik, Ii, R, np;
+  double rho;
+  int nd;
+  long long D;
+  int ddim[MAXC];
+  EdgeRef ekd[MAXC];     // W(j, i_m), m in d (float64 edge matrices)
+  const double* Q;
+  int Rprod, nu, upos_i;
+  int urank[MAXN - 1];
+  long long ustride[MAXN - 1];
+  long long ugoff[MAXN - 1];     // G_{k,m} for each U mode
+  int first, S;
+  const double* Upart;
+  double* Ufin;
+  long long goff_ki, goff_ik;
+  long long w_off;
+  int w_sj, w_sy;
+  double* W64;
+  void* Wc;
+  double* G;
+  double* dgpart;
+};
+
+struct ReconArgs {
+  int N;
+  int dims[MAXN];
+  long long nX;
+  int ne;
+  int ea[10], eb[10];
+  long long woff[10];
+  const void* Wc;
+  void* out;
+};
+
+// kernel classes for timing
+enum KernelClass { KC_CONTRACT = 0, KC_SOLVE = 1, KC_UPDATE = 2, KC_GRAM = 3, KC_COUNT = 4 };
+
+// ---- launchers (ifctn_kernels.hip) ----------------------------------------
+// dtype: 0 = float32 streaming data, 1 = float64
+hipError_t launch_init_x(int dtype, const void* O, const uint8_t* mask, void* X, uint32_t* maskbits,
+                         int* bad_flag, long long nX, hipStream_t s);
+hipError_t launch_edge(int dtype, const double* Gab, const double* Gba, int R, int Ia, int Ib,
+                       double* W64, void* Wc, hipStream_t s);
+hipError_t launch_contract(int dtype, bool upd, bool con, int spt, const ContractArgs& a,
+                           size_t smem, hipStream_t s);
+size_t contract_smem_bytes(int dtype, const ContractArgs& a);
+hipError_t launch_q(const QArgs& a, hipStream_t s);
+hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s);
+size_t solve_smem_bytes(const SolveArgs& a);
+hipError_t launch_reconstruct(int dtype, const ReconArgs& a, hipStream_t s);
+hipError_t launch_finalize(const double* normpart, int nnorm, const double* dgpart, int ndg,
+                           double* out5, hipStream_t s);
+
+}  // namespace ifctn

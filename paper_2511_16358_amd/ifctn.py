@@ -1,0 +1,229 @@
+"""ctypes binding of libifctn.so (include/ifctn.h).
+
+Argument marshalling only: every step of the completion runs in the HIP
+library.  The functions keep the C names; :class:`Job` is a small convenience
+wrapper that takes torch tensors (torch provides device memory and streams).
+The library must be built (``__graft_entry__.build()``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+try:  # load torch's HIP runtime first so that the library shares it
+    import torch
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+
+from . import workloads
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libifctn.so")
+
+IFCTN_MAX_ORDER = 5
+IFCTN_MAX_RANK = 8
+IFCTN_OK, IFCTN_E_INVAL, IFCTN_E_NOMEM, IFCTN_E_HIP, IFCTN_E_STATE, IFCTN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+IFCTN_FP32, IFCTN_BF16_REFINE, IFCTN_FP64 = 0, 1, 2
+KC_CONTRACT, KC_SOLVE, KC_UPDATE, KC_GRAM = 0, 1, 2, 3
+
+EXPORTED = [
+    "ifctn_num_factor_entries", "ifctn_workspace_bytes", "ifctn_init", "ifctn_sweep",
+    "ifctn_reconstruct", "ifctn_get_factors", "ifctn_destroy", "ifctn_complete",
+    "ifctn_assemble", "ifctn_timing_enable", "ifctn_timing_query", "ifctn_last_error",
+]
+
+
+class IfctnParams(ctypes.Structure):
+    _fields_ = [
+        ("order", ctypes.c_int32),
+        ("dims", ctypes.c_int64 * IFCTN_MAX_ORDER),
+        ("ranks", (ctypes.c_int32 * IFCTN_MAX_ORDER) * IFCTN_MAX_ORDER),
+        ("rho", ctypes.c_double),
+        ("rho_x", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("refine_sweeps", ctypes.c_int32),
+    ]
+
+
+class IfctnStats(ctypes.Structure):
+    _fields_ = [
+        ("rel_change", ctypes.c_double),
+        ("objective", ctypes.c_double),
+        ("x_norm2", ctypes.c_double),
+        ("dx_norm2", ctypes.c_double),
+        ("dg_norm2", ctypes.c_double),
+        ("sweeps_done", ctypes.c_int32),
+        ("converged", ctypes.c_int32),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class IfctnError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"ifctn status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libifctn.so (once) and declare the C signatures."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, S = ctypes.POINTER(IfctnParams), ctypes.POINTER(IfctnStats)
+    vp, dp, i32, st = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_int32, ctypes.c_int
+    sig = {
+        "ifctn_num_factor_entries": (ctypes.c_size_t, [P]),
+        "ifctn_workspace_bytes": (ctypes.c_size_t, [P]),
+        "ifctn_init": (st, [P, vp, vp, dp, vp, ctypes.POINTER(vp)]),
+        "ifctn_sweep": (st, [vp, i32, S]),
+        "ifctn_reconstruct": (st, [vp, vp, i32]),
+        "ifctn_get_factors": (st, [vp, dp]),
+        "ifctn_destroy": (st, [vp]),
+        "ifctn_complete": (st, [P, vp, vp, dp, i32, ctypes.c_double, vp, S, vp]),
+        "ifctn_assemble": (st, [P, dp, vp, vp]),
+        "ifctn_timing_enable": (st, [vp, i32]),
+        "ifctn_timing_query": (st, [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]),
+        "ifctn_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(status):
+    if status != IFCTN_OK:
+        raise IfctnError(status, lib().ifctn_last_error().decode())
+
+
+def make_params(dims, ranks, rho=0.1, rho_x=0.0, precision=IFCTN_FP32) -> IfctnParams:
+    p = IfctnParams()
+    p.order = len(dims)
+    for m, d in enumerate(dims):
+        p.dims[m] = int(d)
+    for a in range(len(dims)):
+        for b in range(len(dims)):
+            p.ranks[a][b] = int(ranks[a][b]) if a != b else 0
+    p.rho, p.rho_x, p.precision, p.refine_sweeps = float(rho), float(rho_x), int(precision), 0
+    return p
+
+
+def _dptr(arr: np.ndarray):
+    return arr.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def num_factor_entries(dims, ranks) -> int:
+    return int(lib().ifctn_num_factor_entries(ctypes.byref(make_params(dims, ranks))))
+
+
+def workspace_bytes(dims, ranks, precision=IFCTN_FP32) -> int:
+    return int(lib().ifctn_workspace_bytes(ctypes.byref(make_params(dims, ranks, precision=precision))))
+
+
+def _stream_handle():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dtype(precision):
+    return torch.float64 if precision == IFCTN_FP64 else torch.float32
+
+
+class Job:
+    """A completion job on the current torch device and stream."""
+
+    def __init__(self, O, mask, G0, dims, ranks, rho=0.1, rho_x=0.0, precision=IFCTN_FP32):
+        self.dims = tuple(int(d) for d in dims)
+        self.ranks = np.asarray(ranks)
+        self.precision = precision
+        self.params = make_params(self.dims, self.ranks, rho, rho_x, precision)
+        dt = _dtype(precision)
+        self.O = torch.as_tensor(np.asarray(O)).to(device="cuda", dtype=dt).contiguous()
+        self.mask = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to("cuda").contiguous()
+        g0 = G0 if isinstance(G0, np.ndarray) and G0.ndim == 1 else workloads.pack(G0, self.dims, self.ranks)
+        self._g0 = np.ascontiguousarray(g0, dtype=np.float64)
+        h = ctypes.c_void_p()
+        _check(lib().ifctn_init(ctypes.byref(self.params), ctypes.c_void_p(self.O.data_ptr()),
+                                ctypes.c_void_p(self.mask.data_ptr()), _dptr(self._g0),
+                                _stream_handle(), ctypes.byref(h)))
+        self.handle = h
+
+    def sweep(self, n=1, stats=True):
+        s = IfctnStats()
+        _check(lib().ifctn_sweep(self.handle, int(n), ctypes.byref(s) if stats else None))
+        return s.as_dict() if stats else None
+
+    def reconstruct(self, which=0):
+        out = torch.empty(self.dims, dtype=_dtype(self.precision), device="cuda")
+        _check(lib().ifctn_reconstruct(self.handle, ctypes.c_void_p(out.data_ptr()), int(which)))
+        return out
+
+    def x(self):
+        return self.reconstruct(1)
+
+    def xhat(self):
+        return self.reconstruct(0)
+
+    def factors(self):
+        n = num_factor_entries(self.dims, self.ranks)
+        buf = np.empty(n, dtype=np.float64)
+        _check(lib().ifctn_get_factors(self.handle, _dptr(buf)))
+        return workloads.unpack(buf, self.dims, self.ranks)
+
+    def timing(self, enable: bool):
+        _check(lib().ifctn_timing_enable(self.handle, 1 if enable else 0))
+
+    def timing_query(self, kernel_class):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().ifctn_timing_query(self.handle, int(kernel_class), ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ifctn_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def complete(O, mask, G0, dims, ranks, t_max, eps=0.0, rho=0.1, precision=IFCTN_FP32):
+    """Algorithm 1 end to end through ifctn_complete; returns (X, stats)."""
+    dims = tuple(int(d) for d in dims)
+    params = make_params(dims, ranks, rho, 0.0, precision)
+    dt = _dtype(precision)
+    Ot = torch.as_tensor(np.asarray(O)).to(device="cuda", dtype=dt).contiguous()
+    Mt = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to("cuda").contiguous()
+    g0 = np.ascontiguousarray(workloads.pack(G0, dims, ranks) if isinstance(G0, dict) else G0,
+                              dtype=np.float64)
+    out = torch.empty(dims, dtype=dt, device="cuda")
+    s = IfctnStats()
+    _check(lib().ifctn_complete(ctypes.byref(params), ctypes.c_void_p(Ot.data_ptr()),
+                                ctypes.c_void_p(Mt.data_ptr()), _dptr(g0), int(t_max), float(eps),
+                                ctypes.c_void_p(out.data_ptr()), ctypes.byref(s), _stream_handle()))
+    return out, s.as_dict()
+
+
+def assemble(dims, ranks, G, precision=IFCTN_FP32):
+    """iFCTN(G) materialised on the GPU by the library (eq. (iFCTN))."""
+    dims = tuple(int(d) for d in dims)
+    params = make_params(dims, ranks, precision=precision)
+    g = np.ascontiguousarray(workloads.pack(G, dims, ranks) if isinstance(G, dict) else G, dtype=np.float64)
+    out = torch.empty(dims, dtype=_dtype(precision), device="cuda")
+    _check(lib().ifctn_assemble(ctypes.byref(params), _dptr(g), ctypes.c_void_p(out.data_ptr()),
+                                _stream_handle()))
+    return out

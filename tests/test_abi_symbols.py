@@ -1,0 +1,50 @@
+"""The C-ABI library loads and exports every symbol include/ifctn.h declares
+(no compute calls: runs without a GPU); host-only entry points give the
+paper's storage count and reject invalid parameters."""
+import os
+import re
+
+import pytest
+
+from paper_2511_16358_amd import ifctn, workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "ifctn.h")).read()
+    return sorted(set(re.findall(r"\b(ifctn_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_symbols_exported():
+    L = ifctn.lib()
+    syms = declared_symbols()
+    assert len(syms) >= 12
+    for s in syms:
+        assert hasattr(L, s), s
+    assert sorted(ifctn.EXPORTED) == syms
+
+
+def test_storage_count_matches_paper():
+    # Table 4: iFCTN ranks (4,4,4) on 256x256x31 store 4,344 parameters
+    assert ifctn.num_factor_entries((256, 256, 31), W.uniform_ranks(3, 4)) == 4344
+
+
+@pytest.mark.parametrize("dims,ranks,why", [
+    ((5,), W.uniform_ranks(1, 2), "order"),
+    ((2, 3, 4, 5, 6, 7), W.uniform_ranks(6, 2)[:5, :5], "order"),
+    ((4, 0, 3), W.uniform_ranks(3, 2), "dims"),
+    ((4, 5, 3), [[0, 2, 2], [3, 0, 2], [2, 2, 0]], "symmetric"),
+    ((4, 5, 3), [[0, 0, 2], [0, 0, 2], [2, 2, 0]], "rank"),
+])
+def test_invalid_params_rejected(dims, ranks, why):
+    p = ifctn.make_params(dims[:5], ranks)
+    p.order = len(dims)
+    assert ifctn.lib().ifctn_workspace_bytes(p) == 0
+    assert ifctn.lib().ifctn_num_factor_entries(p) == 0
+
+
+def test_workspace_fits_every_workload():
+    for name, (dims, R, _) in W.CONFIGS.items():
+        b = ifctn.workspace_bytes(dims, W.uniform_ranks(len(dims), R))
+        assert 0 < b < 64 << 20, (name, b)
