@@ -223,23 +223,74 @@ ContractPlan plan_contract(const Geo& g, int k) {
   for (int t = 0; t < 3; ++t)
     if (ord[t] == 0) jpos = t;
 
-  // tiling: an LDS tile of at most `tile` streaming elements, at most 32
-  // float64 accumulators per thread, split partials bounded by a quarter of X
+  const long long budget0 = std::max<long long>(g.nX * (long long)g.esz / 2, 256 << 10);
+  // fast layouts: fibre mode contiguous (rows) or mode k contiguous (columns)
+  if (a.stride_f == 1 || a.stride_k == 1) {
+    a.kind = a.stride_f == 1 ? 1 : 2;
+    a.plfast = (nc > 0 && a.cstride[nc - 1] < a.stride_k) ? 1 : 0;
+    const long long jcapf = std::max<long long>(1, (long long)NT * 8 / a.Rprod);   // <= 8 slots per thread
+    // workgroups of a few thousand elements: enough work to amortise the
+    // per-plane set-up, a few hundred workgroups over the chip
+    const long long E = std::min<long long>(65536, std::max<long long>(4096, g.nX / 320));
+    long long jn = (a.kind == 1 && a.plfast) ? std::min<long long>({(long long)a.Ik, jcapf, 8})
+                                             : std::min<long long>(a.Ik, jcapf);
+    long long JT = cdiv(a.Ik, jn);
+    jn = cdiv(a.Ik, JT);
+    long long PPW = std::max<long long>(1, std::min<long long>(a.nplanes, E / std::max<long long>(1, jn * a.If)));
+    long long S = cdiv(a.nplanes, PPW);
+    while (S * a.Ik * a.Rprod * 8 > budget0 && PPW < a.nplanes) {
+      PPW = std::min<long long>(a.nplanes, PPW * 2);
+      S = cdiv(a.nplanes, PPW);
+    }
+    // columns: split the fibre range too when plane splits alone leave the chip idle
+    long long FS = 1;
+    if (a.kind == 2 && JT * S < 240)
+      FS = std::max<long long>(1, std::min<long long>(cdiv(240, JT * S), a.If / 16));
+    while (FS > 1 && S * FS * a.Ik * a.Rprod * 8 > budget0) --FS;
+    a.FS = (int)FS;
+    a.jn = (int)jn;
+    a.JT = (int)JT;
+    a.S = (int)S;
+    a.PPW = PPW;
+    a.PB = (int)std::min<long long>(PPW, a.kind == 1 ? 64 : 32);
+    a.fch = 1;
+    if (a.kind == 1) {
+      int fch = 1;
+      while (fch < 64 && a.If / (2 * fch) >= 4) fch *= 2;
+      a.fch = fch;
+    }
+    while (a.PB > 1 && contract_smem_bytes(g.dtype, a) > kMaxLds) a.PB = std::max(1, a.PB * 3 / 4);
+    int ps = 1;
+    while (ps < 16 && jn * a.Rprod * ps * 2 <= NT && a.PB >= 2 * ps) ps *= 2;
+    a.psplit = ps;
+    const long long slots = jn * a.Rprod * a.psplit;
+    int spt = 1;
+    while ((long long)spt * NT < slots) spt *= 2;
+    P.spt = spt;
+    P.smem = contract_smem_bytes(g.dtype, a);
+    return P;
+  }
+
+  // generic layout: an LDS tile of at most `tile` streaming elements, at
+  // most 32 float64 accumulators per thread, split partials bounded by half of X
   const long long tile = g.dtype ? 4096 : 8192;
-  const long long budget = std::max<long long>(g.nX * (long long)g.esz / 4, 256 << 10);
+  const long long budget = std::max<long long>(g.nX * (long long)g.esz / 2, 256 << 10);
   const long long smax = std::max<long long>(1, budget / ((long long)a.Ik * a.Rprod * 8));
   const long long jcap = std::max<long long>(1, std::min<long long>((long long)NT * 32 / a.Rprod, tile / a.LDF));
   long long JT, S;
   if (jpos == 0) {
-    // j is the slowest axis: one j per workgroup streams contiguous slices
-    JT = a.Ik;
+    // j is the slowest axis: a few j per workgroup (the per-plane set-up is
+    // shared by the j of a tile), planes split to fill the chip
+    const long long jw = std::min<long long>({(long long)a.Ik, jcap, 8});
+    JT = cdiv(a.Ik, jw);
     S = std::max<long long>(1, std::min<long long>(std::min(smax, a.nplanes), cdiv(kTargetBlocks, JT)));
   } else {
     S = std::max<long long>(1, std::min(smax, a.nplanes));
     const long long jt_min = cdiv(a.Ik, jcap);
     long long jt_max = a.Ik;
-    // j innermost: keep runs of at least 16 consecutive elements
-    if (jpos == 2) jt_max = std::max<long long>(jt_min, cdiv(a.Ik, std::min<long long>(a.Ik, 16)));
+    // j innermost: keep the whole j range (contiguous runs, no cache line
+    // shared by workgroups on different XCDs) unless the slots do not fit
+    if (jpos == 2) jt_max = jt_min;
     JT = std::min(jt_max, std::max(jt_min, cdiv(kTargetBlocks, S)));
   }
   long long jn = cdiv(a.Ik, JT);
@@ -251,11 +302,26 @@ ContractPlan plan_contract(const Geo& g, int k) {
   a.jn = (int)jn;
   a.JT = (int)JT;
   a.S = (int)S;
+  a.FS = 1;
   a.PPW = PPW;
   a.PB = (int)PB;
   // shrink the plane batch until the LDS layout fits
   while (a.PB > 1 && contract_smem_bytes(g.dtype, a) > kMaxLds) a.PB = std::max(1, a.PB * 3 / 4);
-  const long long slots = jn * a.Rprod;
+  // lanes per fibre dot product: enough rows x lanes to cover the workgroup,
+  // at least 4 fibre elements per lane
+  {
+    const long long rows = (long long)a.PB * jn;
+    int fch = 1;
+    while (fch < 64 && rows * fch * 2 <= NT && (a.If + 2 * fch - 1) / (2 * fch) >= 4) fch *= 2;
+    a.fch = fch;
+  }
+  // threads per accumulator slot when there are few slots
+  {
+    int ps = 1;
+    while (ps < 16 && jn * a.Rprod * ps * 2 <= NT && PPW >= 2 * ps) ps *= 2;
+    a.psplit = ps;
+  }
+  const long long slots = jn * a.Rprod * a.psplit;
   int spt = 1;
   while ((long long)spt * NT < slots) spt *= 2;
   P.spt = spt;
@@ -271,8 +337,14 @@ bool plan_ok(const Geo& g, const ContractPlan& P, const char** why) {
   const ContractArgs& a = P.a;
   if ((long long)a.JT * a.jn < a.Ik || (long long)(a.JT - 1) * a.jn >= a.Ik) { *why = "j tiling"; return false; }
   if ((long long)a.S * a.PPW < a.nplanes || (long long)(a.S - 1) * a.PPW >= a.nplanes) { *why = "plane split"; return false; }
+  if (a.FS < 1 || (a.FS > 1 && a.kind != 2) || (long long)(a.FS - 1) * ((a.If + a.FS - 1) / a.FS) >= a.If) { *why = "fibre split"; return false; }
   if ((long long)a.nplanes * a.Ik * a.If != g.nX) { *why = "plane count"; return false; }
-  if ((long long)a.jn * a.Rprod > (long long)P.spt * NT || P.spt > 32) { *why = "accumulator slots"; return false; }
+  if ((long long)a.jn * a.Rprod * a.psplit > (long long)P.spt * NT || P.spt > 32) { *why = "accumulator slots"; return false; }
+  if (a.psplit > 1 && (long long)a.jn * a.Rprod * a.psplit > NT) { *why = "split slots"; return false; }
+  if (a.fch < 1 || a.fch > 64 || (a.fch & (a.fch - 1)) != 0) { *why = "fibre lanes"; return false; }
+  if (a.kind == 1 && a.stride_f != 1) { *why = "rows layout"; return false; }
+  if (a.kind == 2 && a.stride_k != 1) { *why = "columns layout"; return false; }
+  if (a.kind != 0 && (long long)a.PB * a.jn * a.Rf * 0 + (long long)a.psplit * a.jn * a.Rprod > (long long)P.spt * NT) { *why = "fast slots"; return false; }
   if (a.PB < 1 || a.PB > 256 || a.jn < 1) { *why = "batch"; return false; }
   if (P.smem > kMaxLds) { *why = "LDS size"; return false; }
   if (a.Rf > MAXR || a.Rc > 4096) { *why = "rank product"; return false; }
@@ -290,37 +362,38 @@ QArgs plan_q(const Geo& g, int k, long long* qsize) {
   int t = 0;
   for (int i = 0; i < N; ++i) {
     if (i == k) continue;
-    a.Ii[t] = g.dims[i];
-    a.R[t] = g.R[k][i];
-    a.np[t] = a.R[t] * (a.R[t] + 1) / 2;
+    QItem& it = a.it[t];
+    it.Ii = g.dims[i];
+    it.R = g.R[k][i];
+    const int np = it.R * (it.R + 1) / 2;
     int dm[MAXC], nd = 0;
     long long D = 1;
     for (int m = 0; m < N; ++m)
       if (m != k && m != i) dm[nd++] = m;
     for (int c = 0; c < nd; ++c) {
-      a.ddim[t][c] = g.dims[dm[c]];
-      a.edi[t][c] = edge_ref(g, dm[c], i);
+      it.ddim[c] = g.dims[dm[c]];
+      it.edi[c] = edge_ref(g, dm[c], i);
       D *= g.dims[dm[c]];
     }
     int q = 0;
     for (int x = 0; x < nd; ++x)
       for (int y = x + 1; y < nd; ++y) {
-        a.dd_a[t][q] = x;
-        a.dd_b[t][q] = y;
-        a.edd[t][q] = edge_ref(g, dm[x], dm[y]);
+        it.dd_a[q] = x;
+        it.dd_b[q] = y;
+        it.edd[q] = edge_ref(g, dm[x], dm[y]);
         ++q;
       }
-    a.D[t] = D;
-    int lanes = (int)std::min<long long>(64, cdiv(a.Ii[t], 8));
+    it.D = D;
+    int lanes = (int)std::min<long long>(64, cdiv(it.Ii, 8));
     int lg = 0;
     while ((1 << lg) < lanes) ++lg;
-    a.lg2P[t] = lg;
-    a.CH[t] = (int)cdiv(a.Ii[t], 1 << lg);
+    it.lg2P = lg;
+    it.CH = (int)cdiv(it.Ii, 1 << lg);
     a.blk0[t] = blk;
     blk += cdiv(D << lg, NT);
-    a.qoff[t] = qo;
-    qo += D * a.np[t];
-    a.gik[t] = g.goff[i][k];
+    it.qoff = qo;
+    qo += D * np;
+    it.gik = g.goff[i][k];
     ++t;
   }
   a.blk0[t] = blk;
@@ -352,7 +425,7 @@ struct ifctn_job {
   int* flag = nullptr;
   ContractPlan cplan[MAXN];
   QArgs qplan[MAXN];
-  SolveArgs splan[MAXN][MAXN];
+  SolveArgs splan[MAXN];
   int nnorm = 0, ndg = 0;
   bool pending = false;
   int sweeps_done = 0;
@@ -385,18 +458,19 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
     if (dbg) {
       const ContractArgs& a = P.a;
       std::fprintf(stderr,
-                   "[ifctn plan] k=%d f=%d ord=%d%d%d Ik=%d If=%d LDF=%d nc=%d Rf=%d Rc=%d Rprod=%d jn=%d JT=%d S=%d "
-                   "PPW=%lld PB=%d nplanes=%lld spt=%d smem=%zu blocks=%lld upart=%lld | Q blocks=%lld size=%lld\n",
-                   k, a.f, a.ord[0], a.ord[1], a.ord[2], a.Ik, a.If, a.LDF, a.nc, a.Rf, a.Rc, a.Rprod, a.jn, a.JT, a.S, a.PPW, a.PB,
-                   a.nplanes, P.spt, P.smem, (long long)a.JT * a.S, (long long)a.S * a.Ik * a.Rprod,
+                   "[ifctn plan] k=%d f=%d kind=%d plfast=%d ord=%d%d%d Ik=%d If=%d LDF=%d nc=%d Rf=%d Rc=%d Rprod=%d jn=%d JT=%d S=%d "
+                   "PPW=%lld PB=%d FS=%d nplanes=%lld spt=%d fch=%d psplit=%d smem=%zu blocks=%lld upart=%lld | Q blocks=%lld size=%lld\n",
+                   k, a.f, a.kind, a.plfast, a.ord[0], a.ord[1], a.ord[2], a.Ik, a.If, a.LDF, a.nc, a.Rf, a.Rc, a.Rprod, a.jn, a.JT, a.S, a.PPW, a.PB,
+                   a.FS, a.nplanes, P.spt, a.fch, a.psplit, P.smem, (long long)a.JT * a.S * a.FS,
+                   (long long)a.S * a.FS * a.Ik * a.Rprod,
                    Q.blk0[Q.ni], qs);
     }
     if (cp) cp[k] = P;
     if (qp) qp[k] = Q;
     qmax = std::max(qmax, qs);
-    upmax = std::max(upmax, (long long)P.a.S * P.a.Ik * P.a.Rprod);
+    upmax = std::max(upmax, (long long)P.a.S * P.a.FS * P.a.Ik * P.a.Rprod);
     ufmax = std::max(ufmax, (long long)P.a.Ik * P.a.Rprod);
-    if (k == 0) nnorm = (long long)P.a.JT * P.a.S;
+    if (k == 0) nnorm = (long long)P.a.JT * P.a.S * P.a.FS;
     ndg += (long long)(g.N - 1) * g.dims[k];
   }
   s.Q = al256(qmax * 8);
@@ -417,63 +491,67 @@ void build_solve_plans(ifctn_job* J) {
   for (int k = 0; k < N; ++k) {
     const ContractPlan& P = J->cplan[k];
     const QArgs& Q = J->qplan[k];
+    SolveArgs& a = J->splan[k];
+    std::memset(&a, 0, sizeof(a));
+    a.k = k;
+    a.Ik = g.dims[k];
+    a.nsub = N - 1;
+    a.rho = g.rho;
     int umodes[MAXN - 1], nu = 0;
     for (int m = 0; m < N; ++m)
       if (m != k) umodes[nu++] = m;
-    long long ust[MAXN - 1];
-    long long s = 1;
+    a.nu = nu;
+    long long st = 1;
     for (int t = nu - 1; t >= 0; --t) {
-      ust[t] = s;
-      s *= g.R[k][umodes[t]];
+      a.ustride[t] = st;
+      st *= g.R[k][umodes[t]];
     }
+    int ro = 0;
+    for (int t = 0; t < nu; ++t) {
+      const int m = umodes[t];
+      a.udim[t] = g.dims[m];
+      a.urank[t] = g.R[k][m];
+      a.ugoff[t] = g.goff[k][m];
+      a.rowoff[t] = ro;
+      ro += g.dims[m];
+      a.ekm[t] = edge_ref(g, k, m);
+    }
+    a.rowtot = ro;
+    a.Rprod = P.a.Rprod;
+    a.S = P.a.S * P.a.FS;
+    a.Upart = J->Upart;
+    a.W64 = J->W64;
+    a.Wc = J->Wc;
+    a.G = J->G;
+    a.dgpart = J->dgpart + dgo;
+    dgo += (long long)(N - 1) * a.Ik;
     int t = 0;
-    bool first = true;
     for (int i = 0; i < N; ++i) {
       if (i == k) continue;
-      SolveArgs a;
-      std::memset(&a, 0, sizeof(a));
-      a.k = k;
-      a.i = i;
-      a.Ik = g.dims[k];
-      a.Ii = g.dims[i];
-      a.R = g.R[k][i];
-      a.np = a.R * (a.R + 1) / 2;
-      a.rho = g.rho;
-      int dm[MAXC], nd = 0;
-      for (int m = 0; m < N; ++m)
-        if (m != k && m != i) dm[nd++] = m;
-      a.nd = nd;
-      a.D = Q.D[t];
-      for (int c = 0; c < nd; ++c) {
-        a.ddim[c] = g.dims[dm[c]];
-        a.ekd[c] = edge_ref(g, k, dm[c]);
-      }
-      a.Q = J->Q + Q.qoff[t];
-      a.Rprod = P.a.Rprod;
-      a.nu = nu;
+      SubBlock& B = a.sb[t];
+      B.i = i;
+      B.Ii = g.dims[i];
+      B.R = g.R[k][i];
+      B.np = B.R * (B.R + 1) / 2;
+      for (int u = 0; u < nu; ++u)
+        if (umodes[u] == i) B.upos = u;
+      int nd = 0;
       for (int u = 0; u < nu; ++u) {
-        a.urank[u] = g.R[k][umodes[u]];
-        a.ustride[u] = ust[u];
-        a.ugoff[u] = g.goff[k][umodes[u]];
-        if (umodes[u] == i) a.upos_i = u;
+        const int m = umodes[u];
+        if (m == i) continue;
+        B.ddim[nd] = g.dims[m];
+        B.dt[nd] = u;
+        ++nd;
       }
-      a.first = first ? 1 : 0;
-      a.S = P.a.S;
-      a.Upart = J->Upart;
-      a.Ufin = J->Ufin;
-      a.goff_ki = g.goff[k][i];
-      a.goff_ik = g.goff[i][k];
+      B.nd = nd;
+      B.D = Q.it[t].D;
+      B.Q = J->Q + Q.it[t].qoff;
+      B.goff_ki = g.goff[k][i];
+      B.goff_ik = g.goff[i][k];
       const EdgeRef w = edge_ref(g, k, i);
-      a.w_off = w.off;
-      a.w_sj = w.s1;
-      a.w_sy = w.s2;
-      a.W64 = J->W64;
-      a.Wc = J->Wc;
-      a.G = J->G;
-      a.dgpart = J->dgpart + dgo;
-      dgo += a.Ik;
-      J->splan[k][i] = a;
-      first = false;
+      B.w_off = w.off;
+      B.w_sj = w.s1;
+      B.w_sy = w.s2;
       ++t;
     }
   }
@@ -526,11 +604,8 @@ hipError_t run_sweep(ifctn_job* J) {
     ContractCall cc{k, k == 0 && J->pending, true};
     e = timed(J, KC_CONTRACT, do_contract, &cc);
     if (e != hipSuccess) return e;
-    for (int i = 0; i < N; ++i) {
-      if (i == k) continue;
-      e = timed(J, KC_SOLVE, do_solve, &J->splan[k][i]);
-      if (e != hipSuccess) return e;
-    }
+    e = timed(J, KC_SOLVE, do_solve, &J->splan[k]);
+    if (e != hipSuccess) return e;
   }
   J->pending = true;
   J->sweeps_done++;
@@ -636,8 +711,15 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
     J->qplan[k].G = J->G;
     J->qplan[k].Q = J->Q;
   }
-  J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S;
+  J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
   build_solve_plans(J);
+  for (int k = 0; k < g.N; ++k) {
+    if (solve_smem_bytes(J->splan[k]) > kMaxLds) {
+      (void)hipFree(J->arena);
+      delete J;
+      return fail(IFCTN_E_UNSUPPORTED, "mode sizes too large for the factor-block kernel (mode %d)", k);
+    }
+  }
   auto bail = [&](ifctn_status code, const char* what, hipError_t err) {
     ifctn_status r = fail(code, "%s: %s", what, hipGetErrorString(err));
     ifctn_destroy(J);

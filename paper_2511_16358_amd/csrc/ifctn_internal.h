@@ -22,6 +22,26 @@ struct EdgeRef {
   int s1, s2;
 };
 
+// Q_{k,i}(d; r, r') = sum_{i_i} S_k(i_{-k})^2 G_{i,k}(r, i_i) G_{i,k}(r', i_i),
+// d = index over the modes other than k and i; constant during block k.
+struct QItem {               // one i != k
+  int Ii, R, lg2P, CH;        // lanes per d = 2^lg2P (<= 64), fibre chunk per lane
+  long long D, qoff, gik;     // d count, offset of Q_{k,i}, offset of G_{i,k}
+  int ddim[MAXC];
+  EdgeRef edi[MAXC];          // W(i_m, i_i), m in d
+  int dd_a[3], dd_b[3];
+  EdgeRef edd[3];             // W(i_a, i_b), a, b in d
+};
+
+struct QArgs {
+  int ni, nd, ndd;
+  long long blk0[MAXN];       // first workgroup of each i; blk0[ni] = total
+  QItem it[MAXN - 1];
+  const double* W64;
+  const double* G;
+  double* Q;
+};
+
 // Mode-k contraction U_k(j, r_{-k}) = sum_{i_{-k}} X(i) S_k(i_{-k}) prod_{m != k}
 // G_{m,k}(r_m, i_m), organised by "planes": for a fixed index c of the modes
 // other than k and the fibre mode f, the plane is the I_k x I_f slice of X.
@@ -48,6 +68,13 @@ struct ContractArgs {
   // touch consecutive addresses
   int ord[3];
   int jn, PB, JT, S;
+  int fch;               // lanes sharing one fibre dot product (power of two <= 64)
+  int psplit;            // threads sharing one accumulator slot (planes split round-robin)
+  // kernel variant: 0 = generic LDS tile, 1 = rows (fibre mode contiguous,
+  // lanes split each fibre), 2 = columns (mode k contiguous, lanes along j)
+  int kind;
+  int plfast;            // rows: consecutive planes are closer in memory than consecutive j
+  int FS;                // columns: fibre range split over FS workgroups (partials S * FS)
   long long PPW, nplanes;
   // fused X step (k == 0 only)
   EdgeRef e0c[MAXC];     // W(i_0, i_m) for the c-modes
@@ -62,56 +89,40 @@ struct ContractArgs {
   double* normpart;      // [blocks][3]: ||dX||^2, ||X||^2, ||X_new - Xhat||^2
 };
 
-// Q_{k,i}(d; r, r') = sum_{i_i} S_k(i_{-k})^2 G_{i,k}(r, i_i) G_{i,k}(r', i_i),
-// d = index over the modes other than k and i; constant during block k.
-struct QArgs {
-  int ni;
-  int Ii[MAXN - 1];
-  int R[MAXN - 1];
-  int np[MAXN - 1];
-  long long D[MAXN - 1];
-  int lg2P[MAXN - 1];    // log2 of the lanes per d (power of two <= 64)
-  int CH[MAXN - 1];      // fibre chunk per lane
-  long long blk0[MAXN];  // first workgroup of each i; blk0[ni] = total
-  long long qoff[MAXN - 1];
-  long long gik[MAXN - 1];
-  int nd;
-  int ddim[MAXN - 1][MAXC];
-  EdgeRef edi[MAXN - 1][MAXC];   // W(i_m, i_i), m in d
-  int ndd;
-  int dd_a[MAXN - 1][3], dd_b[MAXN - 1][3];
-  EdgeRef edd[MAXN - 1][3];
-  const double* W64;
-  const double* G;
-  double* Q;
-};
-
-// One factor block G_{k,i}: per column j, H_j = sum_d w_j(d) Q(d) + rho I with
-// w_j(d) = prod_{m in d} W_{k,m}(j, i_m)^2, b_j from U_k, Cholesky solve, then
-// the edge matrix of {k,i} is refreshed for that column.
-struct SolveArgs {
-  int k, i;
-  int Ik, Ii, R, np;
-  double rho;
+// Factor block k (all G_{k,i}, i != k, in ascending i), one workgroup per
+// column j.  Column j of every G_{k,i} depends only on row j of the edge
+// matrices of mode k (plus factors owned by other modes, fixed during block
+// k), so the Gauss-Seidel chain over i runs inside the workgroup.
+struct SubBlock {
+  int i, Ii, R, np, upos;
   int nd;
   long long D;
   int ddim[MAXC];
-  EdgeRef ekd[MAXC];     // W(j, i_m), m in d (float64 edge matrices)
-  const double* Q;
-  int Rprod, nu, upos_i;
-  int urank[MAXN - 1];
-  long long ustride[MAXN - 1];
-  long long ugoff[MAXN - 1];     // G_{k,m} for each U mode
-  int first, S;
-  const double* Upart;
-  double* Ufin;
+  int dt[MAXC];          // U-mode index of each d-mode
+  const double* Q;       // Q_{k,i}: [D][np]
   long long goff_ki, goff_ik;
   long long w_off;
-  int w_sj, w_sy;
+  int w_sj, w_sy;        // W_{k,i}(j, y) at w_off + j * w_sj + y * w_sy
+};
+
+struct SolveArgs {
+  int k, Ik, nsub;
+  double rho;
+  SubBlock sb[MAXN - 1];
+  int Rprod, nu;
+  int udim[MAXN - 1];
+  int urank[MAXN - 1];
+  long long ustride[MAXN - 1];
+  long long ugoff[MAXN - 1];     // G_{k,m} for each U mode m (modes != k ascending)
+  int rowoff[MAXN - 1];          // LDS offset of the row W_{k,m}(j, :)
+  int rowtot;
+  EdgeRef ekm[MAXN - 1];         // W(j, i_m) for each U mode (float64 edge matrices)
+  int S;
+  const double* Upart;
   double* W64;
   void* Wc;
   double* G;
-  double* dgpart;
+  double* dgpart;                // [nsub][Ik]
 };
 
 struct ReconArgs {

@@ -13,6 +13,7 @@
 // bitwise reproducible.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 
 #include "ifctn_internal.h"
@@ -33,8 +34,23 @@ __device__ __forceinline__ T ld(const T* p, long long i) {
   return p[i];
 }
 
-__device__ __forceinline__ long long eaddr(const EdgeRef& e, long long a, long long b) {
+__device__ __forceinline__ long long eaddr(const EdgeRef e, long long a, long long b) {
   return e.off + a * e.s1 + b * e.s2;
+}
+
+// for (e = tid; e < n; e += NT) use(e, load(e)), with the loads of U
+// consecutive iterations issued before any of them is consumed (the index is
+// clamped so that every load is in bounds and the body has no branches)
+template <int U, typename Load, typename Use>
+__device__ __forceinline__ void for_batched(int n, Load load, Use use) {
+  for (int eb = threadIdx.x; eb < n; eb += NT * U) {
+    decltype(load(0)) v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = load(min(eb + u * NT, n - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (eb + u * NT < n) use(eb + u * NT, v[u]);
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -77,6 +93,127 @@ __global__ __launch_bounds__(NT) void k_edge(const double* __restrict__ Gab, con
 }
 
 // --------------------------------------------------------------------------
+// K4: Gram weights Q_{k,i} for every i != k of block k (float64).  They
+// depend only on edges not touching k and on factors G_{i,k} of other modes,
+// so they are constant during block k.  Work item = (d, fibre
+// chunk); the lanes of one d are adjacent in a wave and reduce with a fixed
+// butterfly.  The fibre chunk is walked four entries at a time with all
+// loads issued first.
+// --------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void gram_work(const double* __restrict__ W64, const double* __restrict__ Gp,
+                                          double* __restrict__ Qp, int nd, int ndd, const QItem it,
+                                          long long item) {
+  constexpr int NP = R * (R + 1) / 2;
+  const int lg = it.lg2P;
+  const long long dd = item >> lg;
+  const int ch = (int)(item & ((1 << lg) - 1));
+  const int Ii = it.Ii;
+  const bool valid = dd < it.D;
+  double acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = 0.0;
+  if (valid) {
+    int im[MAXC];
+    long long t = dd;
+#pragma unroll
+    for (int c = MAXC - 1; c >= 0; --c) {
+      im[c] = 0;
+      if (c < nd) {
+        im[c] = (int)(t % it.ddim[c]);
+        t /= it.ddim[c];
+      }
+    }
+    double sdd = 1.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (q < ndd) {
+        const int xa = it.dd_a[q], xb = it.dd_b[q];
+        const int ia = xa == 0 ? im[0] : (xa == 1 ? im[1] : im[2]);
+        const int ib = xb == 0 ? im[0] : (xb == 1 ? im[1] : im[2]);
+        const double w = W64[eaddr(it.edd[q], ia, ib)];
+        sdd *= w * w;
+      }
+    }
+    const int lo = ch * it.CH, hi = min(Ii, lo + it.CH);
+    const double* Gik = Gp + it.gik;
+    constexpr int XU = R <= 4 ? 4 : 2;
+    for (int x0 = lo; x0 < hi; x0 += XU) {
+      double wv[XU][MAXC], g[XU][R];
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int x = min(x0 + u, hi - 1);
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) wv[u][c] = c < nd ? W64[eaddr(it.edi[c], im[c], x)] : 1.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) g[u][r] = Gik[(long long)r * Ii + x];
+      }
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const double live = (x0 + u < hi) ? 1.0 : 0.0;
+        double w = sdd * live;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) w *= wv[u][c] * wv[u][c];
+        int p = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double wr = w * g[u][r];
+#pragma unroll
+          for (int s2 = r; s2 < R; ++s2) acc[p++] += wr * g[u][s2];
+        }
+      }
+    }
+  }
+  for (int o = 1; o < (1 << lg); o <<= 1) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] += __shfl_xor(acc[p], o, 64);
+  }
+  if (valid && ch == 0) {
+    double* q = Qp + it.qoff + dd * NP;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) q[p] = acc[p];
+  }
+}
+
+template <int R>
+__device__ __forceinline__ void gram_item(const QArgs& a, int ii, long long item) {
+  // constant-index copies keep the argument block out of scratch memory
+  const double* W64 = a.W64;
+  const double* Gp = a.G;
+  double* Qp = a.Q;
+  const int nd = a.nd, ndd = a.ndd;
+  switch (ii) {
+    case 0: { const QItem it = a.it[0]; gram_work<R>(W64, Gp, Qp, nd, ndd, it, item); break; }
+    case 1: { const QItem it = a.it[1]; gram_work<R>(W64, Gp, Qp, nd, ndd, it, item); break; }
+    case 2: { const QItem it = a.it[2]; gram_work<R>(W64, Gp, Qp, nd, ndd, it, item); break; }
+    default: { const QItem it = a.it[3]; gram_work<R>(W64, Gp, Qp, nd, ndd, it, item); break; }
+  }
+}
+
+__global__ __launch_bounds__(NT) void k_gram_q(QArgs a) {
+  // constant indices only: a runtime index into the argument block would
+  // force a copy of it into scratch memory
+  const long long bid = blockIdx.x;
+  int ii = 0;
+  if (a.ni > 1 && bid >= a.blk0[1]) ii = 1;
+  if (a.ni > 2 && bid >= a.blk0[2]) ii = 2;
+  if (a.ni > 3 && bid >= a.blk0[3]) ii = 3;
+  const long long b0 = ii == 0 ? a.blk0[0] : ii == 1 ? a.blk0[1] : ii == 2 ? a.blk0[2] : a.blk0[3];
+  const long long item = ((long long)blockIdx.x - b0) * NT + threadIdx.x;
+  const int R = ii == 0 ? a.it[0].R : ii == 1 ? a.it[1].R : ii == 2 ? a.it[2].R : a.it[3].R;
+  switch (R) {   // uniform per workgroup
+    case 1: gram_item<1>(a, ii, item); break;
+    case 2: gram_item<2>(a, ii, item); break;
+    case 3: gram_item<3>(a, ii, item); break;
+    case 4: gram_item<4>(a, ii, item); break;
+    case 5: gram_item<5>(a, ii, item); break;
+    case 6: gram_item<6>(a, ii, item); break;
+    case 7: gram_item<7>(a, ii, item); break;
+    default: gram_item<8>(a, ii, item); break;
+  }
+}
+
+// --------------------------------------------------------------------------
 // K3 (+ K6): mode-k contraction, optionally fused with the X step of the
 // previous sweep.
 //
@@ -107,13 +244,15 @@ __host__ __device__ inline CLayout clayout(int tcsz, const ContractArgs& a) {
   L.scc = o;   o = al16(o + (size_t)a.PB * tcsz);
   L.scf = o;   o = al16(o + (size_t)a.PB * a.LDF * tcsz);
   L.t0 = o;    o = al16(o + (size_t)a.PB * a.jn * tcsz);
-  L.tile = o;  o = al16(o + (size_t)a.PB * a.jn * a.LDF * tcsz);
+  L.tile = o;  o = al16(o + std::max((size_t)a.PB * a.jn * a.LDF * tcsz, (size_t)NT * 8));
   L.T = o;     o = al16(o + (size_t)a.PB * a.jn * a.Rf * tcsz);
   L.gf = o;    o = al16(o + (size_t)a.If * a.Rf * tcsz);
   L.red = o;   o = al16(o + 4 * 3 * 8);
   L.total = o;
   return L;
 }
+
+constexpr int UNR = 8;   // X elements in flight per thread in the streaming stage
 
 template <typename TX, typename TC, bool UPD, bool CON, int SPT>
 __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
@@ -130,9 +269,10 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   TC* gf = (TC*)(smem + Ly.gf);
   double* red = (double*)(smem + Ly.red);
 
+  const int bid = (int)blockIdx.x;
   const int tid = threadIdx.x;
-  const int jt = blockIdx.x % a.JT;
-  const int sp = blockIdx.x / a.JT;
+  const int jt = bid % a.JT;
+  const int sp = bid / a.JT;
   const int j0 = jt * a.jn;
   const int jcnt = min(a.jn, a.Ik - j0);
   const long long p_begin = (long long)sp * a.PPW;
@@ -140,29 +280,36 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   const TC* __restrict__ Wc = (const TC*)a.Wc;
   TX* __restrict__ X = (TX*)a.X;
   const double* __restrict__ G = a.G;
-  const int If = a.If, Rf = a.Rf, Rc = a.Rc, Rprod = a.Rprod, nc = a.nc, jn = a.jn;
+  const int If = a.If, Rf = a.Rf, Rc = a.Rc, Rprod = a.Rprod, nc = a.nc, jn = a.jn, LDF = a.LDF;
+  const int psplit = a.psplit;
 
+  // accumulator slots: slot s -> (j, r_c, r_f) and a plane residue class
   double acc[SPT];
-  int aoff[SPT], toff[SPT];
+  int aoff[SPT], toff[SPT], psub[SPT];
 #pragma unroll
   for (int q = 0; q < SPT; ++q) {
     acc[q] = 0.0;
     aoff[q] = -1;
     toff[q] = 0;
+    psub[q] = 0;
     if (CON) {
       const int s = q * NT + tid;
-      if (s < jcnt * Rprod) {
-        const int jl = s / Rprod, col = s - jl * Rprod;
-        aoff[q] = col / Rf;
-        toff[q] = jl * Rf + (col - (col / Rf) * Rf);
+      if (s < jcnt * Rprod * psplit) {
+        const int b = s / psplit;
+        const int jl = b / Rprod, sl = b - jl * Rprod;
+        psub[q] = s - b * psplit;
+        aoff[q] = sl / Rf;
+        toff[q] = jl * Rf + (sl - (sl / Rf) * Rf);
       }
     }
   }
   if (CON) {
-    for (int e = tid; e < Rf * If; e += NT) {
-      const int r = e / If, ff = e - r * If;
-      gf[ff * Rf + r] = (TC)G[a.gfoff + e];
-    }
+    for_batched<4>(
+        Rf * If, [&](int e) { return G[a.gfoff + e]; },
+        [&](int e, double v) {
+          const int r = e / If, ff = e - r * If;
+          gf[ff * Rf + r] = (TC)v;
+        });
   }
   double dx2 = 0.0, x2 = 0.0, f2 = 0.0;
   const TC rx = (TC)a.rho_x;
@@ -170,7 +317,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
 
   for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
     const int np = (int)min((long long)a.PB, p_end - pb0);
-    // (a) planes
+    // (a) planes: base offsets, S_k factors, Kronecker coefficients
     for (int e = tid; e < np; e += NT) {
       long long p = pb0 + e, base = 0;
       int ic[MAXC];
@@ -186,103 +333,169 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       for (int c = 0; c < MAXC; ++c) pidx[e * MAXC + c] = c < nc ? ic[c] : 0;
     }
     __syncthreads();
-    for (int e = tid; e < np * If; e += NT) {
-      const int pl = e / If, ff = e - pl * If;
-      TC s = sccl[pl];
-      for (int c = 0; c < nc; ++c) s *= Wc[eaddr(a.ecf[c], pidx[pl * MAXC + c], ff)];
-      scf[pl * a.LDF + ff] = s;
-    }
+    for_batched<4>(
+        np * If,
+        [&](int e) {
+          const int pl = e / If, ff = e - pl * If;
+          TC s = sccl[pl];
+#pragma unroll
+          for (int c = 0; c < MAXC; ++c)
+            if (c < nc) s *= Wc[eaddr(a.ecf[c], pidx[pl * MAXC + c], ff)];
+          return s;
+        },
+        [&](int e, TC v) {
+          const int pl = e / If;
+          scf[pl * LDF + (e - pl * If)] = v;
+        });
     if (CON) {
-      for (int e = tid; e < np * Rc; e += NT) {
-        const int pl = e / Rc;
-        int rr = e - pl * Rc;
-        double v = 1.0;
-        for (int c = nc - 1; c >= 0; --c) {
-          const int r = rr % a.crank[c];
-          rr /= a.crank[c];
-          v *= G[a.gcoff[c] + (long long)r * a.cdim[c] + pidx[pl * MAXC + c]];
-        }
-        acoef[e] = v;
-      }
+      for_batched<4>(
+          np * Rc,
+          [&](int e) {
+            const int pl = e / Rc;
+            int rr = e - pl * Rc;
+            double v = 1.0;
+#pragma unroll
+            for (int c = MAXC - 1; c >= 0; --c) {
+              if (c < nc) {
+                const int r = rr % a.crank[c];
+                rr /= a.crank[c];
+                v *= G[a.gcoff[c] + (long long)r * a.cdim[c] + pidx[pl * MAXC + c]];
+              }
+            }
+            return v;
+          },
+          [&](int e, double v) { acoef[e] = v; });
     }
     if (UPD) {
-      for (int e = tid; e < np * jcnt; e += NT) {
-        const int pl = e / jcnt, jl = e - pl * jcnt;
-        TC v = (TC)1;
-        for (int c = 0; c < nc; ++c) v *= Wc[eaddr(a.e0c[c], j0 + jl, pidx[pl * MAXC + c])];
-        t0[pl * jn + jl] = v;
-      }
+      for_batched<4>(
+          np * jcnt,
+          [&](int e) {
+            const int pl = e / jcnt, jl = e - pl * jcnt;
+            TC v = (TC)1;
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c)
+              if (c < nc) v *= Wc[eaddr(a.e0c[c], j0 + jl, pidx[pl * MAXC + c])];
+            return v;
+          },
+          [&](int e, TC v) {
+            const int pl = e / jcnt;
+            t0[pl * jn + (e - pl * jcnt)] = v;
+          });
     }
     __syncthreads();
 
-    // (b) stream X: the batch is enumerated over (D0, D1, D2) = extents of the
-    // axes ord[0..2]; a carried mixed-radix counter avoids divisions
+    // (b) stream X.  The batch is enumerated over the extents of the axes
+    // ord[0..2] (slowest memory stride first); a carried mixed-radix counter
+    // replaces divisions, and UNR loads are issued before any is consumed.
     {
-      const int o0 = a.ord[0], o1 = a.ord[1], o2 = a.ord[2];
+      const int o0 = a.ord[0], o1 = a.ord[1];
       const int D0 = o0 == 0 ? jcnt : (o0 == 1 ? np : If);
       const int D1 = o1 == 0 ? jcnt : (o1 == 1 ? np : If);
-      const int D2 = o2 == 0 ? jcnt : (o2 == 1 ? np : If);
-      const long long total = (long long)D0 * D1 * D2;
+      const int D2 = (o0 != 0 && o1 != 0) ? jcnt : ((o0 != 1 && o1 != 1) ? np : If);
+      const int total = D0 * D1 * D2;
       const int s2 = NT % D2, s1 = (NT / D2) % D1, s0 = NT / (D1 * D2);
       int i2 = tid % D2, i1 = (tid / D2) % D1, i0 = tid / (D1 * D2);
-      for (long long e = tid; e < total; e += NT) {
-        const int jl = o0 == 0 ? i0 : (o1 == 0 ? i1 : i2);
-        const int pl = o0 == 1 ? i0 : (o1 == 1 ? i1 : i2);
-        const int ff = o0 == 2 ? i0 : (o1 == 2 ? i1 : i2);
-        const long long L = pbase[pl] + (long long)(j0 + jl) * a.stride_k + (long long)ff * a.stride_f;
-        TC x = (TC)X[L];
-        const TC sk = scf[pl * a.LDF + ff];
-        if (UPD) {
-          const TC xh = sk * t0[pl * jn + jl] * Wc[eaddr(a.e0f, j0 + jl, ff)];
-          const bool obs = (a.maskbits[L >> 5] >> (L & 31)) & 1u;
-          const TC xn = obs ? x : (xh + rx * x) * inv1;
-          if (!obs) X[L] = (TX)xn;
-          const double d = (double)xn - (double)x;
-          dx2 += d * d;
-          x2 += (double)x * (double)x;
-          const double rr = (double)xn - (double)xh;
-          f2 += rr * rr;
-          x = xn;
+      for (int eb = tid; eb < total; eb += NT * UNR) {
+        long long Lv[UNR];
+        int pv[UNR], jv[UNR], fv[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const bool ok = eb + u * NT < total;
+          const int jl = o0 == 0 ? i0 : (o1 == 0 ? i1 : i2);
+          const int pl = o0 == 1 ? i0 : (o1 == 1 ? i1 : i2);
+          const int ff = (o0 != 2 && o1 != 2) ? i2 : (o0 == 2 ? i0 : i1);
+          jv[u] = ok ? jl : 0;
+          pv[u] = ok ? pl : 0;
+          fv[u] = ok ? ff : 0;
+          // out-of-range lanes load element (0, 0, 0) of the batch and drop it
+          Lv[u] = pbase[pv[u]] + (long long)(j0 + jv[u]) * a.stride_k + (long long)fv[u] * a.stride_f;
+          if (!ok) Lv[u] = -1 - Lv[u];
+          i2 += s2;
+          if (i2 >= D2) { i2 -= D2; ++i1; }
+          i1 += s1;
+          if (i1 >= D1) { i1 -= D1; ++i0; }
+          i0 += s0;
         }
-        if (CON) tile[(pl * jn + jl) * a.LDF + ff] = x * sk;
-        i2 += s2;
-        if (i2 >= D2) { i2 -= D2; ++i1; }
-        i1 += s1;
-        if (i1 >= D1) { i1 -= D1; ++i0; }
-        i0 += s0;
+        TX xr[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) xr[u] = X[Lv[u] >= 0 ? Lv[u] : -1 - Lv[u]];
+        uint32_t mw[UNR];
+        TC w0[UNR];
+        if (UPD) {
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            mw[u] = a.maskbits[(Lv[u] >= 0 ? Lv[u] : -1 - Lv[u]) >> 5];
+            w0[u] = Wc[eaddr(a.e0f, j0 + jv[u], fv[u])];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          if (Lv[u] < 0) continue;
+          TC x = (TC)xr[u];
+          const TC sk = scf[pv[u] * LDF + fv[u]];
+          if (UPD) {
+            const TC xh = sk * t0[pv[u] * jn + jv[u]] * w0[u];
+            const bool obs = (mw[u] >> (Lv[u] & 31)) & 1u;
+            const TC xn = obs ? x : (xh + rx * x) * inv1;
+            if (!obs) X[Lv[u]] = (TX)xn;
+            const double d = (double)xn - (double)x;
+            dx2 += d * d;
+            x2 += (double)x * (double)x;
+            const double rr = (double)xn - (double)xh;
+            f2 += rr * rr;
+            x = xn;
+          }
+          if (CON) tile[(pv[u] * jn + jv[u]) * LDF + fv[u]] = x * sk;
+        }
       }
     }
     __syncthreads();
 
     if (CON) {
-      // (c) fibre contraction
+      // (c) fibre contraction T(row, r_f), each row shared by fch adjacent lanes
       const int rows = np * jcnt;
-      for (int row = tid; row < rows; row += NT) {
-        const int pl = row / jcnt, jl = row - pl * jcnt;
+      const int fch = a.fch;
+      const int rpp = NT / fch;
+      const int chunk = (If + fch - 1) / fch;
+      const int ch = tid & (fch - 1);
+      const int passes = (rows + rpp - 1) / rpp;
+      for (int ps = 0; ps < passes; ++ps) {
+        const int row = ps * rpp + tid / fch;
         TC t[MAXR];
 #pragma unroll
         for (int r = 0; r < MAXR; ++r) t[r] = (TC)0;
-        const TC* trow = tile + (pl * jn + jl) * a.LDF;
-        for (int ff = 0; ff < If; ++ff) {
-          const TC v = trow[ff];
-          const TC* g = gf + ff * Rf;
+        if (row < rows) {
+          const int pl = row / jcnt, jl = row - pl * jcnt;
+          const TC* trow = tile + (pl * jn + jl) * LDF;
+          const int lo = ch * chunk, hi = min(If, lo + chunk);
+          for (int ff = lo; ff < hi; ++ff) {
+            const TC v = trow[ff];
+            const TC* g = gf + ff * Rf;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+              if (r < Rf) t[r] += v * g[r];
+          }
+        }
+        for (int o = 1; o < fch; o <<= 1) {
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r) t[r] += __shfl_xor(t[r], o, 64);
+        }
+        if (row < rows && ch == 0) {
+          const int pl = row / jcnt, jl = row - pl * jcnt;
 #pragma unroll
           for (int r = 0; r < MAXR; ++r)
-            if (r < Rf) t[r] += v * g[r];
+            if (r < Rf) Tl[(pl * jn + jl) * Rf + r] = t[r];
         }
-#pragma unroll
-        for (int r = 0; r < MAXR; ++r)
-          if (r < Rf) Tl[(pl * jn + jl) * Rf + r] = t[r];
       }
       __syncthreads();
-      // (d) Kronecker accumulation into owned slots
+      // (d) Kronecker accumulation into owned slots (planes split round-robin)
 #pragma unroll
       for (int q = 0; q < SPT; ++q) {
         if (aoff[q] >= 0) {
-          double s = acc[q];
-          for (int pl = 0; pl < np; ++pl)
-            s += acoef[pl * Rc + aoff[q]] * (double)Tl[pl * jn * Rf + toff[q]];
-          acc[q] = s;
+          double sum = acc[q];
+          for (int pl = psub[q]; pl < np; pl += psplit)
+            sum += acoef[pl * Rc + aoff[q]] * (double)Tl[pl * jn * Rf + toff[q]];
+          acc[q] = sum;
         }
       }
     }
@@ -290,12 +503,23 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
   }
 
   if (CON) {
+    // combine the plane residue classes in a fixed order, then write the
+    // slot's canonical U column (modes != k ascending, row-major)
+    double* comb = (double*)(smem + Ly.tile);   // tile is free now; psplit > 1 implies <= NT slots
+    if (psplit > 1) {
+#pragma unroll
+      for (int q = 0; q < SPT; ++q)
+        if (aoff[q] >= 0) comb[q * NT + tid] = acc[q];
+      __syncthreads();
+    }
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
-      if (aoff[q] >= 0) {
+      if (aoff[q] >= 0 && psub[q] == 0) {
         const int s = q * NT + tid;
-        const int jl = s / Rprod, sl = s - jl * Rprod;
-        // slot (r_c, r_f) -> canonical U column (modes != k ascending, row-major)
+        double v = acc[q];
+        for (int t = 1; t < psplit; ++t) v += comb[s + t];
+        const int b = s / psplit;
+        const int jl = b / Rprod, sl = b - jl * Rprod;
         int rc = sl / Rf;
         long long col = (long long)(sl - rc * Rf) * a.ustf;
         for (int c = nc - 1; c >= 0; --c) {
@@ -303,7 +527,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
           rc /= a.crank[c];
           col += (long long)r * a.ustc[c];
         }
-        a.Upart[((long long)sp * a.Ik + j0 + jl) * Rprod + col] = acc[q];
+        a.Upart[((long long)sp * a.Ik + j0 + jl) * Rprod + col] = v;
       }
     }
   }
@@ -317,88 +541,503 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
     }
     __syncthreads();
     if (tid < 3) {
-      double s = 0.0;
-      for (int q = 0; q < NT / 64; ++q) s += red[q * 3 + tid];
-      a.normpart[(long long)blockIdx.x * 3 + tid] = s;
+      double sum = 0.0;
+      for (int q = 0; q < NT / 64; ++q) sum += red[q * 3 + tid];
+      a.normpart[(long long)bid * 3 + tid] = sum;
     }
   }
 }
 
 // --------------------------------------------------------------------------
-// K4: Gram weights Q_{k,i} for every i != k of block k (float64).
-// Work item = (d, fibre chunk); the lanes of one d are adjacent in a wave and
-// reduce with a fixed butterfly.
+// K3 fast paths.  Same contraction as k_contract, for the two layouts every
+// tensor of this library's workloads uses, with X read from HBM straight into
+// registers (no LDS tile):
+//   rows:    the fibre mode f is the contiguous last mode; each fibre (plane,
+//            j) is split over `fch` adjacent lanes that reduce with a fixed
+//            butterfly;
+//   columns: mode k is the contiguous last mode; lanes run along j (coalesced)
+//            and loop over the fibre, fibre chunks reduced through LDS in a
+//            fixed order.
+// Both finish like k_contract: T(plane, j, r_f) in LDS, then the Kronecker
+// accumulation into float64 slots and the split partials of U_k.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_gram_q(QArgs a) {
-  int ii = 0;
-  while (ii + 1 < a.ni && (long long)blockIdx.x >= a.blk0[ii + 1]) ++ii;
-  const long long item = ((long long)blockIdx.x - a.blk0[ii]) * NT + threadIdx.x;
-  const int lg = a.lg2P[ii];
-  const long long dd = item >> lg;
-  const int ch = (int)(item & ((1 << lg) - 1));
-  const int R = a.R[ii], np = a.np[ii], Ii = a.Ii[ii];
-  const bool valid = dd < a.D[ii];
-  double acc[MAXP];
+struct FLayout {
+  size_t pbase, pidx, acoef, scc, scf, t0, w0f, gf, T, tpart, red, total;
+};
+
+__host__ __device__ inline FLayout flayout(int tcsz, const ContractArgs& a) {
+  FLayout L;
+  size_t o = 0;
+  L.pbase = o; o = al16(o + (size_t)a.PB * 8);
+  L.pidx = o;  o = al16(o + (size_t)a.PB * MAXC * 4);
+  L.acoef = o; o = al16(o + (size_t)a.PB * a.Rc * 8);
+  L.scc = o;   o = al16(o + (size_t)a.PB * tcsz);
+  L.scf = o;   o = al16(o + (size_t)a.PB * a.If * tcsz);
+  L.t0 = o;    o = al16(o + (size_t)a.PB * a.jn * tcsz);
+  L.w0f = o;   o = al16(o + (size_t)(a.k == 0 ? a.jn * a.If : 0) * tcsz);
+  L.gf = o;    o = al16(o + (size_t)a.If * MAXR * tcsz);      // zero-padded to MAXR ranks
+  L.T = o;     o = al16(o + std::max((size_t)a.PB * a.jn * a.Rf * tcsz, (size_t)NT * 8));
+  L.tpart = o; o = al16(o + (a.kind == 2 ? (size_t)NT * a.Rf * tcsz : 0));
+  L.red = o;   o = al16(o + 4 * 3 * 8);
+  L.total = o;
+  return L;
+}
+
+// shared pieces of the fast kernels (NC = number of modes other than k and f,
+// a compile-time constant so that no load sits behind a per-mode branch) -----
+template <typename TC, int NC>
+__device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0, int np, int jcnt, int j0,
+                                            long long* pbase, int* pidx, TC* sccl, TC* scf, double* acoef,
+                                            TC* t0, bool con, bool upd) {
+  const TC* __restrict__ Wc = (const TC*)a.Wc;
+  const int tid = threadIdx.x, If = a.If, Rc = a.Rc, jn = a.jn;
+  for (int e = tid; e < np; e += NT) {
+    long long p = pb0 + e, base = 0;
+    int ic[MAXC > 0 ? MAXC : 1];
 #pragma unroll
-  for (int p = 0; p < MAXP; ++p) acc[p] = 0.0;
-  if (valid) {
-    int im[MAXC];
-    long long t = dd;
-    for (int c = a.nd - 1; c >= 0; --c) {
-      im[c] = (int)(t % a.ddim[ii][c]);
-      t /= a.ddim[ii][c];
+    for (int c = NC - 1; c >= 0; --c) {
+      ic[c] = (int)(p % a.cdim[c]);
+      p /= a.cdim[c];
+      base += (long long)ic[c] * a.cstride[c];
     }
-    double sdd = 1.0;
-    for (int q = 0; q < a.ndd; ++q) {
-      const double w = a.W64[eaddr(a.edd[ii][q], im[a.dd_a[ii][q]], im[a.dd_b[ii][q]])];
-      sdd *= w * w;
-    }
-    const int lo = ch * a.CH[ii], hi = min(Ii, lo + a.CH[ii]);
-    const double* Gik = a.G + a.gik[ii];
-    for (int x = lo; x < hi; ++x) {
-      double w = sdd;
-      for (int c = 0; c < a.nd; ++c) {
-        const double v = a.W64[eaddr(a.edi[ii][c], im[c], x)];
-        w *= v * v;
-      }
-      double g[MAXR];
+    TC sv = (TC)1;
 #pragma unroll
-      for (int r = 0; r < MAXR; ++r) g[r] = r < R ? Gik[(long long)r * Ii + x] : 0.0;
-      // acc holds the upper triangle in a fixed MAXR layout (compile-time slots)
+    for (int x = 0; x < NC; ++x)
 #pragma unroll
-      for (int r = 0; r < MAXR; ++r) {
+      for (int y = x + 1; y < NC; ++y) sv *= Wc[eaddr(a.ecc[x * (2 * NC - x - 1) / 2 + (y - x - 1)], ic[x], ic[y])];
+    pbase[e] = base;
+    sccl[e] = sv;
 #pragma unroll
-        for (int s = r; s < MAXR; ++s) acc[r * MAXR - r * (r - 1) / 2 + (s - r)] += w * g[r] * g[s];
+    for (int c = 0; c < NC; ++c) pidx[e * MAXC + c] = ic[c];
+  }
+  __syncthreads();
+  for_batched<4>(
+      np * If,
+      [&](int e) {
+        const int pl = e / If, ff = e - pl * If;
+        TC v = sccl[pl];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v *= Wc[eaddr(a.ecf[c], pidx[pl * MAXC + c], ff)];
+        return v;
+      },
+      [&](int e, TC v) { scf[e] = v; });
+  if (con) {
+    for_batched<4>(
+        np * Rc,
+        [&](int e) {
+          const int pl = e / Rc;
+          int rr = e - pl * Rc;
+          double v = 1.0;
+#pragma unroll
+          for (int c = NC - 1; c >= 0; --c) {
+            const int r = rr % a.crank[c];
+            rr /= a.crank[c];
+            v *= a.G[a.gcoff[c] + (long long)r * a.cdim[c] + pidx[pl * MAXC + c]];
+          }
+          return v;
+        },
+        [&](int e, double v) { acoef[e] = v; });
+  }
+  if (upd) {
+    for_batched<4>(
+        np * jcnt,
+        [&](int e) {
+          const int pl = e / jcnt, jl = e - pl * jcnt;
+          TC v = (TC)1;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) v *= Wc[eaddr(a.e0c[c], j0 + jl, pidx[pl * MAXC + c])];
+          return v;
+        },
+        [&](int e, TC v) {
+          const int pl = e / jcnt;
+          t0[pl * jn + (e - pl * jcnt)] = v;
+        });
+  }
+  __syncthreads();
+}
+
+// G_{f,k} as gf[f][r] zero-padded to MAXR ranks (unconditional FMAs later)
+template <typename TC>
+__device__ __forceinline__ void load_gf(const ContractArgs& a, TC* gf) {
+  const int If = a.If, Rf = a.Rf;
+  for_batched<4>(
+      If * MAXR,
+      [&](int e) {
+        const int ff = e / MAXR, r = e - ff * MAXR;
+        return r < Rf ? a.G[a.gfoff + (long long)r * If + ff] : 0.0;
+      },
+      [&](int e, double v) { gf[e] = (TC)v; });
+}
+
+template <int SPT>
+struct Slots {
+  double acc[SPT];
+  int aoff[SPT], toff[SPT];
+  int psub;
+  __device__ __forceinline__ void init(int jcnt, int Rprod, int Rf, int psplit) {
+    const int tid = threadIdx.x;
+    psub = tid % psplit;            // NT is a multiple of psplit: the same for every slot
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      acc[q] = 0.0;
+      aoff[q] = -1;
+      toff[q] = 0;
+      const int s = q * NT + tid;
+      if (s < jcnt * Rprod * psplit) {
+        const int b = s / psplit;
+        const int jl = b / Rprod, sl = b - jl * Rprod;
+        aoff[q] = sl / Rf;
+        toff[q] = jl * Rf + (sl - (sl / Rf) * Rf);
       }
     }
   }
-  for (int o = 1; o < (1 << lg); o <<= 1) {
+  // planes outer, slots inner: the 2 SPT LDS reads of a plane are issued together
+  template <typename TC>
+  __device__ __forceinline__ void accumulate(const double* acoef, const TC* Tl, int np, int jn, int Rc, int Rf,
+                                             int psplit) {
+    int ao[SPT], to[SPT];
 #pragma unroll
-    for (int p = 0; p < MAXP; ++p) acc[p] += __shfl_xor(acc[p], o, 64);
-  }
-  if (valid && ch == 0) {
-    // packed upper triangle for the runtime rank: p(r, s) = r R - r (r - 1) / 2 + (s - r)
-    double* q = a.Q + a.qoff[ii] + dd * np;
-#pragma unroll
-    for (int r = 0; r < MAXR; ++r) {
-#pragma unroll
-      for (int s = r; s < MAXR; ++s)
-        if (s < R) q[r * R - r * (r - 1) / 2 + (s - r)] = acc[r * MAXR - r * (r - 1) / 2 + (s - r)];
+    for (int q = 0; q < SPT; ++q) {
+      ao[q] = aoff[q] >= 0 ? aoff[q] : 0;
+      to[q] = toff[q];
     }
+    for (int pl = psub; pl < np; pl += psplit) {
+      double av[SPT], tv[SPT];
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        av[q] = acoef[pl * Rc + ao[q]];
+        tv[q] = (double)Tl[pl * jn * Rf + to[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) acc[q] += av[q] * tv[q];
+    }
+  }
+  // combine the plane residue classes in a fixed order and write the slot's
+  // canonical U column (modes != k ascending, row-major)
+  template <int NC>
+  __device__ __forceinline__ void write(const ContractArgs& a, double* comb, int sp, int j0) {
+    const int tid = threadIdx.x, psplit = a.psplit, Rprod = a.Rprod, Rf = a.Rf;
+    if (psplit > 1) {
+#pragma unroll
+      for (int q = 0; q < SPT; ++q)
+        if (aoff[q] >= 0) comb[q * NT + tid] = acc[q];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      if (aoff[q] >= 0 && psub == 0) {
+        const int s = q * NT + tid;
+        double v = acc[q];
+        for (int t = 1; t < psplit; ++t) v += comb[s + t];
+        const int b = s / psplit;
+        const int jl = b / Rprod, sl = b - jl * Rprod;
+        int rc = sl / Rf;
+        long long col = (long long)(sl - rc * Rf) * a.ustf;
+#pragma unroll
+        for (int c = NC - 1; c >= 0; --c) {
+          const int r = rc % a.crank[c];
+          rc /= a.crank[c];
+          col += (long long)r * a.ustc[c];
+        }
+        a.Upart[((long long)sp * a.Ik + j0 + jl) * Rprod + col] = v;
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ void block_norms(double dx2, double x2, double f2, double* red, double* out) {
+  const int tid = threadIdx.x;
+  const double v0 = wave_sum(dx2), v1 = wave_sum(x2), v2 = wave_sum(f2);
+  const int w = tid >> 6;
+  if ((tid & 63) == 0) {
+    red[w * 3 + 0] = v0;
+    red[w * 3 + 1] = v1;
+    red[w * 3 + 2] = v2;
+  }
+  __syncthreads();
+  if (tid < 3) {
+    double sum = 0.0;
+    for (int q = 0; q < NT / 64; ++q) sum += red[q * 3 + tid];
+    out[tid] = sum;
   }
 }
 
+// rows variant (fibre mode contiguous) ---------------------------------------
+template <typename TX, typename TC, int NC, bool UPD, bool CON, int SPT>
+__global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const FLayout Ly = flayout((int)sizeof(TC), a);
+  long long* pbase = (long long*)(smem + Ly.pbase);
+  int* pidx = (int*)(smem + Ly.pidx);
+  double* acoef = (double*)(smem + Ly.acoef);
+  TC* sccl = (TC*)(smem + Ly.scc);
+  TC* scf = (TC*)(smem + Ly.scf);
+  TC* t0 = (TC*)(smem + Ly.t0);
+  TC* w0f = (TC*)(smem + Ly.w0f);
+  TC* gf = (TC*)(smem + Ly.gf);
+  TC* Tl = (TC*)(smem + Ly.T);
+  double* red = (double*)(smem + Ly.red);
+
+  const int tid = threadIdx.x, bid = blockIdx.x;
+  const int jt = bid % a.JT, sp = bid / a.JT;
+  const int j0 = jt * a.jn, jcnt = min(a.jn, a.Ik - j0);
+  const long long p_begin = (long long)sp * a.PPW, p_end = min(a.nplanes, p_begin + a.PPW);
+  const TC* __restrict__ Wc = (const TC*)a.Wc;
+  TX* __restrict__ X = (TX*)a.X;
+  const int If = a.If, Rf = a.Rf, jn = a.jn;
+
+  Slots<SPT> sl;
+  if (CON) {
+    sl.init(jcnt, a.Rprod, Rf, a.psplit);
+    load_gf<TC>(a, gf);
+  }
+  if (UPD)
+    for_batched<4>(
+        jcnt * If,
+        [&](int e) {
+          const int jl = e / If, ff = e - jl * If;
+          return Wc[eaddr(a.e0f, j0 + jl, ff)];
+        },
+        [&](int e, TC v) { w0f[e] = v; });
+  double dx2 = 0.0, x2 = 0.0, f2 = 0.0;
+  const TC rx = (TC)a.rho_x, inv1 = (TC)1 / ((TC)1 + rx);
+  const int fch = a.fch, rpp = NT / fch, chunk = (If + fch - 1) / fch, ch = tid & (fch - 1);
+
+  for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
+    const int np = (int)min((long long)a.PB, p_end - pb0);
+    plane_setup<TC, NC>(a, pb0, np, jcnt, j0, pbase, pidx, sccl, scf, acoef, t0, CON, UPD);
+    const int rows = np * jcnt;
+    const int passes = (rows + rpp - 1) / rpp;
+    for (int ps = 0; ps < passes; ++ps) {
+      const int row = ps * rpp + tid / fch;
+      TC t[MAXR];
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) t[r] = (TC)0;
+      const bool rok = row < rows;
+      const int rowc = rok ? row : rows - 1;
+      const int pl = a.plfast ? rowc % np : rowc / jcnt;
+      const int jl = a.plfast ? rowc / np : rowc % jcnt;
+      const long long base = pbase[pl] + (long long)(j0 + jl) * a.stride_k;
+      const TC* sr = scf + pl * If;
+      const TC* wr = w0f + jl * If;
+      const TC tt = UPD ? t0[pl * jn + jl] : (TC)0;
+      const int lo = ch * chunk, hi = rok ? min(If, lo + chunk) : lo;
+      for (int f0 = lo; f0 < hi; f0 += 4) {
+        TX xv[4];
+        uint32_t mw[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long long L = base + min(f0 + u, hi - 1);
+          xv[u] = X[L];
+          if (UPD) mw[u] = a.maskbits[L >> 5];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ff = min(f0 + u, hi - 1);
+          const bool live = f0 + u < hi;
+          TC x = (TC)xv[u];
+          const TC sk = sr[ff];
+          if (UPD) {
+            const long long L = base + ff;
+            const TC xh = sk * tt * wr[ff];
+            const bool obs = (mw[u] >> (L & 31)) & 1u;
+            const TC xn = obs ? x : (xh + rx * x) * inv1;
+            if (live && !obs) X[L] = (TX)xn;
+            const double lv = live ? 1.0 : 0.0;
+            const double d = (double)xn - (double)x;
+            dx2 += lv * d * d;
+            x2 += lv * (double)x * (double)x;
+            const double rr = (double)xn - (double)xh;
+            f2 += lv * rr * rr;
+            x = xn;
+          }
+          if (CON) {
+            const TC y = live ? x * sk : (TC)0;
+            const TC* g = gf + ff * MAXR;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) t[r] += y * g[r];
+          }
+        }
+      }
+      if (CON) {
+        for (int o = 1; o < fch; o <<= 1) {
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r) t[r] += __shfl_xor(t[r], o, 64);
+        }
+        if (rok && ch == 0) {
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r)
+            if (r < Rf) Tl[(pl * jn + jl) * Rf + r] = t[r];
+        }
+      }
+    }
+    __syncthreads();
+    if (CON) sl.accumulate(acoef, Tl, np, jn, a.Rc, Rf, a.psplit);
+    __syncthreads();
+  }
+  if (CON) sl.template write<NC>(a, (double*)(smem + Ly.T), sp, j0);
+  if (UPD) block_norms(dx2, x2, f2, red, a.normpart + (long long)bid * 3);
+}
+
+// columns variant (mode k contiguous) ----------------------------------------
+template <typename TX, typename TC, int NC, int SPT>
+__global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const FLayout Ly = flayout((int)sizeof(TC), a);
+  long long* pbase = (long long*)(smem + Ly.pbase);
+  int* pidx = (int*)(smem + Ly.pidx);
+  double* acoef = (double*)(smem + Ly.acoef);
+  TC* sccl = (TC*)(smem + Ly.scc);
+  TC* scf = (TC*)(smem + Ly.scf);
+  TC* t0 = (TC*)(smem + Ly.t0);
+  TC* gf = (TC*)(smem + Ly.gf);
+  TC* Tl = (TC*)(smem + Ly.T);
+  TC* tpart = (TC*)(smem + Ly.tpart);
+
+  const int tid = threadIdx.x, bid = blockIdx.x;
+  const int jt = bid % a.JT, spf = bid / a.JT;          // partial index = plane split * FS + fibre split
+  const int sp = spf / a.FS, fs = spf - sp * a.FS;
+  const int j0 = jt * a.jn, jcnt = min(a.jn, a.Ik - j0);
+  const long long p_begin = (long long)sp * a.PPW, p_end = min(a.nplanes, p_begin + a.PPW);
+  const TX* __restrict__ X = (const TX*)a.X;
+  const int If = a.If, Rf = a.Rf, jn = a.jn;
+  const int fcs = (If + a.FS - 1) / a.FS, flo = fs * fcs, fhi = min(If, flo + fcs);
+  const long long sf = a.stride_f;
+
+  Slots<SPT> sl;
+  sl.init(jcnt, a.Rprod, Rf, a.psplit);
+  load_gf<TC>(a, gf);
+
+  for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
+    const int np = (int)min((long long)a.PB, p_end - pb0);
+    plane_setup<TC, NC>(a, pb0, np, jcnt, j0, pbase, pidx, sccl, scf, acoef, t0, true, false);
+    const int NI = np * jcnt;                     // (plane, j) columns of this batch
+    const int fg = NI >= NT ? 1 : NT / NI;        // fibre groups within the workgroup
+    const int fchunk = (fhi - flo + fg - 1) / fg;
+    const int npass = fg > 1 ? 1 : (NI + NT - 1) / NT;
+    for (int ps = 0; ps < npass; ++ps) {
+      const int g = fg > 1 ? tid / NI : 0;
+      const int it = fg > 1 ? tid - g * NI : ps * NT + tid;
+      const bool ok = g < fg && it < NI;
+      const int itc = ok ? it : NI - 1;
+      TC t[MAXR];
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) t[r] = (TC)0;
+      const int pl = itc / jcnt, jl = itc - pl * jcnt;
+      const TC* sr = scf + pl * If;
+      const long long base = pbase[pl] + j0 + jl;
+      const int lo = flo + (ok ? g : 0) * fchunk, hi = ok ? min(fhi, lo + fchunk) : lo;
+      for (int f0 = lo; f0 < hi; f0 += 4) {
+        TX xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = X[base + (long long)min(f0 + u, hi - 1) * sf];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ff = min(f0 + u, hi - 1);
+          const TC y = (f0 + u < hi) ? (TC)xv[u] * sr[ff] : (TC)0;
+          const TC* gg = gf + ff * MAXR;
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r) t[r] += y * gg[r];
+        }
+      }
+      if (fg > 1) {
+        if (ok) {
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r)
+            if (r < Rf) tpart[(g * NI + it) * Rf + r] = t[r];
+        }
+        __syncthreads();
+        for (int e = tid; e < NI * Rf; e += NT) {
+          TC v = (TC)0;
+          for (int q = 0; q < fg; ++q) v += tpart[q * NI * Rf + e];
+          const int i2 = e / Rf, r = e - i2 * Rf;
+          const int p2 = i2 / jcnt, j2 = i2 - p2 * jcnt;
+          Tl[(p2 * jn + j2) * Rf + r] = v;
+        }
+      } else if (ok) {
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r)
+          if (r < Rf) Tl[(pl * jn + jl) * Rf + r] = t[r];
+      }
+    }
+    __syncthreads();
+    sl.accumulate(acoef, Tl, np, jn, a.Rc, Rf, a.psplit);
+    __syncthreads();
+  }
+  sl.template write<NC>(a, (double*)(smem + Ly.T), spf, j0);
+}
+
 // --------------------------------------------------------------------------
-// K5: one factor block G_{k,i}, one workgroup per column j.
+// K5: factor block k: for every i != k (ascending), column j of G_{k,i} by
+// eq. (updateG) in float64, one workgroup per column j.
+//   H_j = sum_d w_j(d) Q_{k,i}(d) + rho I,  w_j(d) = prod_{m in d} W_{k,m}(j, i_m)^2
+//   b_j(r_i) = rho g_old + sum_{r_{-k,-i}} prod_{m != k,i} G_{k,m}(r_m, j) U_k(j, r_{-k})
+// then a Cholesky solve, and row j of W_{k,i} is refreshed (kept in LDS for
+// the next i of this column, written to HBM for later blocks).
 // --------------------------------------------------------------------------
 constexpr int TD = 512;   // d-tile staged in LDS
 
-__host__ __device__ inline size_t solve_layout(const SolveArgs& a, size_t* o_u, size_t* o_w, size_t* o_part,
-                                               size_t* o_gk, size_t* o_misc) {
+// Solve (H + rho I) x = b for SPD H given as its packed upper triangle
+// (p(r, s) = r R - r (r - 1) / 2 + (s - r)), by L D L^T; returns ||x - g_old||^2.
+template <int R>
+__device__ __forceinline__ double ldlt_solve(const double* Hs, const double* bs, double rho,
+                                             const double* gold, double* x_out) {
+  double A[R][R], L[R][R], d[R], inv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = r; c < R; ++c) {
+      const double v = Hs[r * R - r * (r - 1) / 2 + (c - r)] + (r == c ? rho : 0.0);
+      A[r][c] = v;
+      A[c][r] = v;
+    }
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    double dc = A[c][c];
+#pragma unroll
+    for (int q = 0; q < c; ++q) dc -= L[c][q] * L[c][q] * d[q];
+    d[c] = dc;
+    inv[c] = 1.0 / dc;
+#pragma unroll
+    for (int r = c + 1; r < R; ++r) {
+      double v = A[r][c];
+#pragma unroll
+      for (int q = 0; q < c; ++q) v -= L[r][q] * L[c][q] * d[q];
+      L[r][c] = v * inv[c];
+    }
+  }
+  double y[R], x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    double v = bs[r];
+#pragma unroll
+    for (int q = 0; q < r; ++q) v -= L[r][q] * y[q];
+    y[r] = v;
+  }
+#pragma unroll
+  for (int r = R - 1; r >= 0; --r) {
+    double v = y[r] * inv[r];
+#pragma unroll
+    for (int q = r + 1; q < R; ++q) v -= L[q][r] * x[q];
+    x[r] = v;
+  }
+  double dg = 0.0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    x_out[r] = x[r];
+    const double e = x[r] - gold[r];
+    dg += e * e;
+  }
+  return dg;
+}
+
+__host__ __device__ inline size_t solve_layout(const SolveArgs& a, size_t* o_u, size_t* o_rows, size_t* o_w,
+                                               size_t* o_part, size_t* o_gk, size_t* o_misc) {
   size_t o = 0;
   *o_u = o;    o = al16(o + (size_t)a.Rprod * 8);
+  *o_rows = o; o = al16(o + (size_t)a.rowtot * 8);
   *o_w = o;    o = al16(o + (size_t)TD * 8);
-  *o_part = o; o = al16(o + (size_t)NT * 8);
+  *o_part = o; o = al16(o + (size_t)2 * NT * 8);
   *o_gk = o;   o = al16(o + (size_t)(MAXN - 1) * MAXR * 8);
   *o_misc = o; o = al16(o + (size_t)(MAXP + 3 * MAXR + 8) * 8);
   return o;
@@ -407,11 +1046,13 @@ __host__ __device__ inline size_t solve_layout(const SolveArgs& a, size_t* o_u, 
 template <typename TC>
 __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-  size_t ou, ow, op, og, om;
-  solve_layout(a, &ou, &ow, &op, &og, &om);
+  size_t ou, orw, ow, op, og, om;
+  solve_layout(a, &ou, &orw, &ow, &op, &og, &om);
   double* u = (double*)(smem + ou);
+  double* rows = (double*)(smem + orw);
   double* wl = (double*)(smem + ow);
   double* part = (double*)(smem + op);
+  double* partb = part + NT;
   double* gk = (double*)(smem + og);
   double* Hs = (double*)(smem + om);
   double* bs = Hs + MAXP;
@@ -420,158 +1061,166 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
 
   const int tid = threadIdx.x;
   const int j = blockIdx.x;
-  const int R = a.R, np = a.np, Ik = a.Ik;
+  const int Ik = a.Ik;
   double* G = a.G;
+  TC* Wc = (TC*)a.Wc;
 
-  // U_k row j: reduce the split partials in fixed order (first block of k)
-  for (int col = tid; col < a.Rprod; col += NT) {
-    double s;
-    if (a.first) {
-      s = 0.0;
-      for (int q = 0; q < a.S; ++q) s += a.Upart[((long long)q * Ik + j) * a.Rprod + col];
-      a.Ufin[(long long)j * a.Rprod + col] = s;
-    } else {
-      s = a.Ufin[(long long)j * a.Rprod + col];
-    }
-    u[col] = s;
-  }
-  // own-side factor columns G_{k,m}(:, j) for the U modes, and g_old
+  // rows W_{k,m}(j, :) and own-side columns G_{k,m}(:, j) of every U mode
+  for_batched<4>(
+      a.rowtot,
+      [&](int e) {
+        int t = 0;
+        while (t + 1 < a.nu && e >= a.rowoff[t + 1]) ++t;
+        return a.W64[eaddr(a.ekm[t], j, e - a.rowoff[t])];
+      },
+      [&](int e, double v) { rows[e] = v; });
   for (int e = tid; e < a.nu * MAXR; e += NT) {
     const int t = e / MAXR, r = e - t * MAXR;
-    gk[e] = (t != a.upos_i && r < a.urank[t]) ? G[a.ugoff[t] + (long long)r * Ik + j] : 0.0;
+    gk[e] = r < a.urank[t] ? G[a.ugoff[t] + (long long)r * Ik + j] : 0.0;
   }
-  if (tid < R) gold[tid] = G[a.goff_ki + (long long)tid * Ik + j];
-
-  // H_j = sum_d w_j(d) Q(d) over d-tiles; thread (p, c) sums d = c mod cpp
-  const int cpp = NT / np;
-  const int p_me = tid % np, c_me = tid / np;
-  double hacc = 0.0;
-  for (long long d0 = 0; d0 < a.D; d0 += TD) {
-    const int nd_t = (int)min((long long)TD, a.D - d0);
-    __syncthreads();
-    for (int e = tid; e < nd_t; e += NT) {
-      long long t = d0 + e;
-      double w = 1.0;
-      for (int c = a.nd - 1; c >= 0; --c) {
-        const int im = (int)(t % a.ddim[c]);
-        t /= a.ddim[c];
-        const double v = a.W64[eaddr(a.ekd[c], j, im)];
-        w *= v * v;
+  // U_k row j: the split partials reduced in a fixed order
+  if (a.Rprod < NT) {
+    const int nch = min(a.S, NT / a.Rprod);
+    const int col = tid % a.Rprod, c = tid / a.Rprod;
+    double v = 0.0;
+    if (c < nch) {
+      const double* up = a.Upart + (long long)j * a.Rprod + col;
+      const long long stride = (long long)Ik * a.Rprod;
+      int q = c;
+      for (; q + 7 * nch < a.S; q += 8 * nch) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = up[(long long)(q + u * nch) * stride];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v += x[u];
       }
-      wl[e] = w;
+      for (; q < a.S; q += nch) v += up[(long long)q * stride];
     }
+    part[tid] = v;
     __syncthreads();
-    if (c_me < cpp) {
-      for (int e = c_me; e < nd_t; e += cpp) hacc += wl[e] * a.Q[(d0 + e) * np + p_me];
+    if (tid < a.Rprod) {
+      double sum = 0.0;
+      for (int q = 0; q < nch; ++q) sum += part[q * a.Rprod + tid];
+      u[tid] = sum;
+    }
+  } else {
+    for (int col = tid; col < a.Rprod; col += NT) {
+      double sum = 0.0;
+      for (int q = 0; q < a.S; ++q) sum += a.Upart[((long long)q * Ik + j) * a.Rprod + col];
+      u[col] = sum;
     }
   }
   __syncthreads();
-  part[tid] = (c_me < cpp) ? hacc : 0.0;
-  __syncthreads();
-  if (tid < np) {
-    double s = 0.0;
-    for (int c = 0; c < cpp; ++c) s += part[c * np + tid];
-    Hs[tid] = s;
-  }
-  __syncthreads();
 
-  // b_j(r_i) = sum over the other U indices of prod_{m != k,i} G_{k,m}(r_m, j) U(j, r)
-  const int cpr = NT / R;
-  const int r_me = tid % R, cb = tid / R;
-  const int nother = a.Rprod / a.urank[a.upos_i];
-  double bacc = 0.0;
-  if (cb < cpr) {
-    for (int o = cb; o < nother; o += cpr) {
-      int rem = o;
-      long long col = (long long)r_me * a.ustride[a.upos_i];
-      double coef = 1.0;
-      for (int t = a.nu - 1; t >= 0; --t) {
-        if (t == a.upos_i) continue;
-        const int r = rem % a.urank[t];
-        rem /= a.urank[t];
-        col += (long long)r * a.ustride[t];
-        coef *= gk[t * MAXR + r];
-      }
-      bacc += coef * u[col];
-    }
-  }
-  part[tid] = (cb < cpr) ? bacc : 0.0;
-  __syncthreads();
-  if (tid < R) {
-    double s = 0.0;
-    for (int c = 0; c < cpr; ++c) s += part[c * R + tid];
-    bs[tid] = s + a.rho * gold[tid];
-  }
-  __syncthreads();
-
-  // Cholesky solve of (H + rho I) g = b (R <= 8, one lane; unrolled over the
-  // maximal rank so that the factor stays in registers)
-  if (tid == 0) {
-    double L[MAXR][MAXR];
-#pragma unroll
-    for (int r = 0; r < MAXR; ++r)
-#pragma unroll
-      for (int s = 0; s < MAXR; ++s) L[r][s] = 0.0;
-#pragma unroll
-    for (int r = 0; r < MAXR; ++r)
-#pragma unroll
-      for (int s = r; s < MAXR; ++s)
-        if (s < R) L[s][r] = Hs[r * R - r * (r - 1) / 2 + (s - r)] + (r == s ? a.rho : 0.0);
-#pragma unroll
-    for (int c = 0; c < MAXR; ++c) {
-      if (c < R) {
-        double d = L[c][c];
-#pragma unroll
-        for (int q = 0; q < c; ++q) d -= L[c][q] * L[c][q];
-        d = sqrt(d);
-        L[c][c] = d;
-#pragma unroll
-        for (int r = c + 1; r < MAXR; ++r) {
-          double v = L[r][c];
-#pragma unroll
-          for (int q = 0; q < c; ++q) v -= L[r][q] * L[c][q];
-          L[r][c] = v / d;
+  for (int t = 0; t < a.nsub; ++t) {
+    const SubBlock& B = a.sb[t];
+    const int R = B.R, np = B.np;
+    // H_j partials over d-tiles (thread (p, c) sums d = c mod cpp) and, in the
+    // same phase, b_j partials (thread (r_i, c) sums the other U indices)
+    const int cpp = NT / np;
+    const int p_me = tid % np, c_me = tid / np;
+    double hacc = 0.0;
+    for (long long d0 = 0; d0 < B.D; d0 += TD) {
+      const int nd_t = (int)min((long long)TD, B.D - d0);
+      for (int e = tid; e < nd_t; e += NT) {
+        long long x = d0 + e;
+        double w = 1.0;
+        for (int c = B.nd - 1; c >= 0; --c) {
+          const int im = (int)(x % B.ddim[c]);
+          x /= B.ddim[c];
+          const double v = rows[a.rowoff[B.dt[c]] + im];
+          w *= v * v;
         }
+        wl[e] = w;
+      }
+      __syncthreads();
+      if (c_me < cpp) {
+        const double* qp = B.Q + d0 * np + p_me;
+        int e = c_me;
+        for (; e + 7 * cpp < nd_t; e += 8 * cpp) {
+          double qv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) qv[u] = qp[(long long)(e + u * cpp) * np];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) hacc += wl[e + u * cpp] * qv[u];
+        }
+        for (; e < nd_t; e += cpp) hacc += wl[e] * qp[(long long)e * np];
+      }
+      if (d0 + TD < B.D) __syncthreads();
+    }
+    const int cpr = NT / R;
+    const int r_me = tid % R, cb = tid / R;
+    const int nother = a.Rprod / R;
+    double bacc = 0.0;
+    if (cb < cpr) {
+      for (int o = cb; o < nother; o += cpr) {
+        int rem = o;
+        long long col = (long long)r_me * a.ustride[B.upos];
+        double coef = 1.0;
+        for (int q = a.nu - 1; q >= 0; --q) {
+          if (q == B.upos) continue;
+          const int r = rem % a.urank[q];
+          rem /= a.urank[q];
+          col += (long long)r * a.ustride[q];
+          coef *= gk[q * MAXR + r];
+        }
+        bacc += coef * u[col];
       }
     }
-    double y[MAXR], x[MAXR];
-#pragma unroll
-    for (int r = 0; r < MAXR; ++r) {
-      double v = r < R ? bs[r] : 0.0;
-#pragma unroll
-      for (int q = 0; q < r; ++q) v -= L[r][q] * y[q];
-      y[r] = r < R ? v / L[r][r] : 0.0;
+    part[tid] = (c_me < cpp) ? hacc : 0.0;
+    partb[tid] = (cb < cpr) ? bacc : 0.0;
+    __syncthreads();
+    if (tid < np) {
+      double sum = 0.0;
+      for (int c = 0; c < cpp; ++c) sum += part[c * np + tid];
+      Hs[tid] = sum;
+    } else if (tid >= 64 && tid < 64 + R) {
+      const int r = tid - 64;
+      double sum = 0.0;
+      for (int c = 0; c < cpr; ++c) sum += partb[c * R + r];
+      gold[r] = gk[B.upos * MAXR + r];
+      bs[r] = sum + a.rho * gold[r];
     }
-#pragma unroll
-    for (int r = MAXR - 1; r >= 0; --r) {
-      double v = y[r];
-#pragma unroll
-      for (int q = r + 1; q < MAXR; ++q) v -= L[q][r] * x[q];
-      x[r] = r < R ? v / L[r][r] : 0.0;
-    }
-    double dg = 0.0;
-#pragma unroll
-    for (int r = 0; r < MAXR; ++r) {
-      if (r < R) {
-        gnew[r] = x[r];
-        const double dd = x[r] - gold[r];
-        dg += dd * dd;
-        G[a.goff_ki + (long long)r * Ik + j] = x[r];
-      }
-    }
-    a.dgpart[j] = dg;
-  }
-  __syncthreads();
+    __syncthreads();
 
-  // refresh the edge matrix of {k, i} for this column of G_{k,i}
-  TC* Wc = (TC*)a.Wc;
-  const double* Gik = G + a.goff_ik;
-  for (int y = tid; y < a.Ii; y += NT) {
-    double s = 0.0;
-    for (int r = 0; r < R; ++r) s += gnew[r] * Gik[(long long)r * a.Ii + y];
-    const long long ad = a.w_off + (long long)j * a.w_sj + (long long)y * a.w_sy;
-    a.W64[ad] = s;
-    Wc[ad] = (TC)s;
+    // (H + rho I) g = b by a square-root-free Cholesky (L D L^T) on one lane,
+    // generated for the exact rank: R reciprocals, no divisions in the sweeps
+    if (tid == 0) {
+      double dg = 0.0;
+      switch (R) {
+        case 1: dg = ldlt_solve<1>(Hs, bs, a.rho, gold, gnew); break;
+        case 2: dg = ldlt_solve<2>(Hs, bs, a.rho, gold, gnew); break;
+        case 3: dg = ldlt_solve<3>(Hs, bs, a.rho, gold, gnew); break;
+        case 4: dg = ldlt_solve<4>(Hs, bs, a.rho, gold, gnew); break;
+        case 5: dg = ldlt_solve<5>(Hs, bs, a.rho, gold, gnew); break;
+        case 6: dg = ldlt_solve<6>(Hs, bs, a.rho, gold, gnew); break;
+        case 7: dg = ldlt_solve<7>(Hs, bs, a.rho, gold, gnew); break;
+        default: dg = ldlt_solve<8>(Hs, bs, a.rho, gold, gnew); break;
+      }
+      for (int r = 0; r < R; ++r) {
+        gk[B.upos * MAXR + r] = gnew[r];
+        G[B.goff_ki + (long long)r * Ik + j] = gnew[r];
+      }
+      a.dgpart[(long long)t * Ik + j] = dg;
+    }
+    __syncthreads();
+
+    // row j of W_{k,i} from the new column: LDS copy for the next i, HBM for later blocks
+    const double* Gik = G + B.goff_ik;
+    for (int y = tid; y < B.Ii; y += NT) {
+      double gv[MAXR];
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) gv[r] = r < R ? Gik[(long long)r * B.Ii + y] : 0.0;
+      double sum = 0.0;
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r)
+        if (r < R) sum += gnew[r] * gv[r];
+      rows[a.rowoff[B.upos] + y] = sum;
+      const long long ad = B.w_off + (long long)j * B.w_sj + (long long)y * B.w_sy;
+      a.W64[ad] = sum;
+      Wc[ad] = (TC)sum;
+    }
+    __syncthreads();
   }
 }
 
@@ -646,6 +1295,7 @@ hipError_t launch_edge(int dtype, const double* Gab, const double* Gba, int R, i
 }
 
 size_t contract_smem_bytes(int dtype, const ContractArgs& a) {
+  if (a.kind != 0) return flayout(dtype == 0 ? 4 : 8, a).total;
   return clayout(dtype == 0 ? 4 : 8, a).total;
 }
 
@@ -667,8 +1317,47 @@ static hipError_t contract_dispatch(bool upd, bool con, int spt, const ContractA
   return hipErrorInvalidValue;
 }
 
+template <typename TX, typename TC, int NC>
+static hipError_t fast_dispatch_nc(bool upd, bool con, int spt, const ContractArgs& a, size_t smem, hipStream_t s) {
+  const dim3 grid((unsigned)(a.JT * a.S * a.FS)), blk(NT);
+  if (a.kind == 1) {
+#define IFCTN_ROWS(U, C, P)                                                              \
+  if (upd == U && con == C && spt == P) {                                                \
+    hipLaunchKernelGGL((k_contract_rows<TX, TC, NC, U, C, P>), grid, blk, smem, s, a);   \
+    return hipGetLastError();                                                            \
+  }
+    IFCTN_ROWS(true, false, 1)
+    IFCTN_ROWS(false, true, 1) IFCTN_ROWS(false, true, 2) IFCTN_ROWS(false, true, 4) IFCTN_ROWS(false, true, 8)
+    IFCTN_ROWS(true, true, 1) IFCTN_ROWS(true, true, 2) IFCTN_ROWS(true, true, 4) IFCTN_ROWS(true, true, 8)
+#undef IFCTN_ROWS
+  } else if (a.kind == 2 && con && !upd) {
+#define IFCTN_COLS(P)                                                              \
+  if (spt == P) {                                                                  \
+    hipLaunchKernelGGL((k_contract_cols<TX, TC, NC, P>), grid, blk, smem, s, a);   \
+    return hipGetLastError();                                                      \
+  }
+    IFCTN_COLS(1) IFCTN_COLS(2) IFCTN_COLS(4) IFCTN_COLS(8)
+#undef IFCTN_COLS
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename TX, typename TC>
+static hipError_t fast_dispatch(bool upd, bool con, int spt, const ContractArgs& a, size_t smem, hipStream_t s) {
+  switch (a.nc) {
+    case 0: return fast_dispatch_nc<TX, TC, 0>(upd, con, spt, a, smem, s);
+    case 1: return fast_dispatch_nc<TX, TC, 1>(upd, con, spt, a, smem, s);
+    case 2: return fast_dispatch_nc<TX, TC, 2>(upd, con, spt, a, smem, s);
+    default: return fast_dispatch_nc<TX, TC, 3>(upd, con, spt, a, smem, s);
+  }
+}
+
 hipError_t launch_contract(int dtype, bool upd, bool con, int spt, const ContractArgs& a, size_t smem,
                            hipStream_t s) {
+  if (a.kind != 0) {
+    if (dtype == 0) return fast_dispatch<float, float>(upd, con, spt, a, smem, s);
+    return fast_dispatch<double, double>(upd, con, spt, a, smem, s);
+  }
   if (dtype == 0) return contract_dispatch<float, float>(upd, con, spt, a, smem, s);
   return contract_dispatch<double, double>(upd, con, spt, a, smem, s);
 }
@@ -680,8 +1369,8 @@ hipError_t launch_q(const QArgs& a, hipStream_t s) {
 }
 
 size_t solve_smem_bytes(const SolveArgs& a) {
-  size_t o1, o2, o3, o4, o5;
-  return solve_layout(a, &o1, &o2, &o3, &o4, &o5);
+  size_t o1, o2, o3, o4, o5, o6;
+  return solve_layout(a, &o1, &o2, &o3, &o4, &o5, &o6);
 }
 
 hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s) {

@@ -76,6 +76,10 @@ def simulate(dims, R, plan):
             rc //= Rk[cm[c]]
         slot_to_col.append(col)
     assert sorted(slot_to_col) == list(range(Rprod))
+    kind = int(plan.get("kind", 0))
+    FS = int(plan.get("FS", 1))
+    if kind != 0:
+        return simulate_fast(dims, plan, kind, FS, strides, cm, cdim, slot_to_col)
     count = np.zeros(nX, dtype=np.int64)
     ucount = np.zeros((S, Ik, Rprod), dtype=np.int64)
     for blk in range(JT * S):
@@ -87,8 +91,11 @@ def simulate(dims, R, plan):
         assert pe > pb
         # slot ownership: s = q*256 + tid < jcnt*Rprod -> (j, slot) -> canonical
         # U column (modes != k ascending, row-major) as the kernel computes it
-        for s in range(jcnt * Rprod):
-            ucount[sp, j0 + s // Rprod, slot_to_col[s % Rprod]] += 1
+        psplit = int(plan["psplit"])
+        assert jcnt * Rprod * psplit <= int(plan["spt"]) * 256
+        for s in range(0, jcnt * Rprod * psplit, psplit):     # the psub == 0 owner writes
+            b = s // psplit
+            ucount[sp, j0 + b // Rprod, slot_to_col[b % Rprod]] += 1
         for pb0 in range(pb, pe, PB):
             npl = min(PB, pe - pb0)
             p = np.arange(pb0, pb0 + npl)
@@ -107,6 +114,68 @@ def simulate(dims, R, plan):
             L = base[pl] + (j0 + jl) * strides[k] + ff * strides[f]
             assert L.min() >= 0 and L.max() < nX
             np.add.at(count, L, 1)
+    return count, ucount
+
+
+def simulate_fast(dims, plan, kind, FS, strides, cm, cdim, slot_to_col):
+    """Replay k_contract_rows (kind 1) / k_contract_cols (kind 2)."""
+    N = len(dims)
+    k, f = int(plan["k"]), int(plan["f"])
+    Ik, If = int(plan["Ik"]), int(plan["If"])
+    jn, JT, S, PPW, PB = (int(plan[x]) for x in ("jn", "JT", "S", "PPW", "PB"))
+    nplanes, Rprod, psplit = int(plan["nplanes"]), int(plan["Rprod"]), int(plan["psplit"])
+    plfast, fch = int(plan["plfast"]), int(plan["fch"])
+    nX = int(np.prod(dims))
+    if kind == 1:
+        assert strides[f] == 1
+    else:
+        assert strides[k] == 1
+    count = np.zeros(nX, dtype=np.int64)
+    ucount = np.zeros((S * FS, Ik, Rprod), dtype=np.int64)
+    for blk in range(JT * S * FS):
+        jt, spf = blk % JT, blk // JT
+        sp, fs = spf // FS, spf % FS
+        j0 = jt * jn
+        jcnt = min(jn, Ik - j0)
+        assert jcnt >= 1
+        pb, pe = sp * PPW, min(nplanes, sp * PPW + PPW)
+        assert pe > pb
+        assert jcnt * Rprod * psplit <= int(plan["spt"]) * 256
+        for s in range(0, jcnt * Rprod * psplit, psplit):
+            b = s // psplit
+            ucount[spf, j0 + b // Rprod, slot_to_col[b % Rprod]] += 1
+        fcs = -(-If // FS)
+        flo, fhi = fs * fcs, min(If, fs * fcs + fcs)
+        assert fhi > flo
+        for pb0 in range(pb, pe, PB):
+            npl = min(PB, pe - pb0)
+            p = np.arange(pb0, pb0 + npl)
+            base = np.zeros(npl, dtype=np.int64)
+            t = p.copy()
+            for c in reversed(range(len(cm))):
+                base += (t % cdim[c]) * strides[cm[c]]
+                t //= cdim[c]
+            if kind == 1:
+                rows = np.arange(npl * jcnt)
+                pl = rows % npl if plfast else rows // jcnt
+                jl = rows // npl if plfast else rows % jcnt
+                chunk = -(-If // fch)
+                assert chunk * fch >= If
+                ff = np.arange(If)
+                L = (base[pl] + (j0 + jl) * strides[k])[:, None] + ff[None, :]
+            else:
+                NI = npl * jcnt
+                fg = 1 if NI >= 256 else 256 // NI
+                fchunk = -(-(fhi - flo) // fg)
+                assert fg * fchunk >= fhi - flo and fg * NI <= 256 or fg == 1
+                it = np.arange(NI)
+                pl, jl = it // jcnt, it % jcnt
+                ff = np.arange(flo, fhi)
+                L = (base[pl] + j0 + jl)[:, None] + ff[None, :] * strides[f]
+            assert L.min() >= 0 and L.max() < nX
+            np.add.at(count, L.ravel(), 1)
+    if FS > 1 or kind == 2:
+        pass
     return count, ucount
 
 
