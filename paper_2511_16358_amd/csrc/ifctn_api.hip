@@ -437,7 +437,7 @@ struct ifctn_job {
 namespace {
 
 struct Sizes {
-  size_t x, bits, G, W64, Wc, Q, Upart, Ufin, normpart, dgpart, stats, flag, total;
+  size_t x, bits, G, W64, Wc, Q, Upart, Ufin, normpart, dgpart, stats, flag, qitems, total;
 };
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -480,7 +480,9 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
   s.dgpart = al256(ndg * 8);
   s.stats = al256(8 * 8);
   s.flag = al256(16);
-  s.total = s.x + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.normpart + s.dgpart + s.stats + s.flag;
+  s.qitems = al256(sizeof(QItem) * MAXN * (MAXN - 1));
+  s.total = s.x + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.normpart + s.dgpart + s.stats + s.flag +
+            s.qitems;
   return s;
 }
 
@@ -699,6 +701,7 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
   J->dgpart = (double*)p;        p += s.dgpart;
   J->stats5 = (double*)p;        p += s.stats;
   J->flag = (int*)p;             p += s.flag;
+  QItem* dq = (QItem*)p;         p += s.qitems;
   for (int k = 0; k < g.N; ++k) {
     ContractArgs& a = J->cplan[k].a;
     a.X = J->X;
@@ -710,6 +713,7 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
     J->qplan[k].W64 = J->W64;
     J->qplan[k].G = J->G;
     J->qplan[k].Q = J->Q;
+    J->qplan[k].dit = dq + (size_t)k * (MAXN - 1);
   }
   J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
   build_solve_plans(J);
@@ -734,6 +738,9 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
   INIT_TRY(hipMemsetAsync(J->dgpart, 0, s.dgpart, J->stream));
   INIT_TRY(hipMemsetAsync(J->flag, 0, s.flag, J->stream));
   INIT_TRY(hipMemcpyAsync(J->G, G0_host, g.nG * 8, hipMemcpyHostToDevice, J->stream));
+  for (int k = 0; k < g.N; ++k)
+    INIT_TRY(hipMemcpyAsync((void*)J->qplan[k].dit, J->qplan[k].it, sizeof(QItem) * (MAXN - 1),
+                            hipMemcpyHostToDevice, J->stream));
   INIT_TRY(launch_init_x(g.dtype, O_dev, mask_dev, J->X, J->bits, J->flag, g.nX, J->stream));
   for (int e2 = 0; e2 < g.ne; ++e2) {
     const int a = g.ea[e2], b = g.eb[e2];

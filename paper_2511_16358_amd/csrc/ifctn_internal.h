@@ -36,7 +36,8 @@ struct QItem {               // one i != k
 struct QArgs {
   int ni, nd, ndd;
   long long blk0[MAXN];       // first workgroup of each i; blk0[ni] = total
-  QItem it[MAXN - 1];
+  QItem it[MAXN - 1];         // host copy (plans, sizes)
+  const QItem* dit;           // device copy read by the kernel
   const double* W64;
   const double* G;
   double* Q;

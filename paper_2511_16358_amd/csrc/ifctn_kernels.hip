@@ -175,41 +175,27 @@ __device__ __forceinline__ void gram_work(const double* __restrict__ W64, const 
   }
 }
 
-template <int R>
-__device__ __forceinline__ void gram_item(const QArgs& a, int ii, long long item) {
-  // constant-index copies keep the argument block out of scratch memory
-  const double* W64 = a.W64;
-  const double* Gp = a.G;
-  double* Qp = a.Q;
-  const int nd = a.nd, ndd = a.ndd;
-  switch (ii) {
-    case 0: { const QItem it = a.it[0]; gram_work<R>(W64, Gp, Qp, nd, ndd, it, item); break; }
-    case 1: { const QItem it = a.it[1]; gram_work<R>(W64, Gp, Qp, nd, ndd, it, item); break; }
-    case 2: { const QItem it = a.it[2]; gram_work<R>(W64, Gp, Qp, nd, ndd, it, item); break; }
-    default: { const QItem it = a.it[3]; gram_work<R>(W64, Gp, Qp, nd, ndd, it, item); break; }
-  }
-}
-
 __global__ __launch_bounds__(NT) void k_gram_q(QArgs a) {
-  // constant indices only: a runtime index into the argument block would
-  // force a copy of it into scratch memory
+  // constant indices into the argument block; the per-i records come from
+  // device memory (a runtime index into the argument block would force a
+  // copy of it into scratch memory)
   const long long bid = blockIdx.x;
   int ii = 0;
   if (a.ni > 1 && bid >= a.blk0[1]) ii = 1;
   if (a.ni > 2 && bid >= a.blk0[2]) ii = 2;
   if (a.ni > 3 && bid >= a.blk0[3]) ii = 3;
   const long long b0 = ii == 0 ? a.blk0[0] : ii == 1 ? a.blk0[1] : ii == 2 ? a.blk0[2] : a.blk0[3];
-  const long long item = ((long long)blockIdx.x - b0) * NT + threadIdx.x;
-  const int R = ii == 0 ? a.it[0].R : ii == 1 ? a.it[1].R : ii == 2 ? a.it[2].R : a.it[3].R;
-  switch (R) {   // uniform per workgroup
-    case 1: gram_item<1>(a, ii, item); break;
-    case 2: gram_item<2>(a, ii, item); break;
-    case 3: gram_item<3>(a, ii, item); break;
-    case 4: gram_item<4>(a, ii, item); break;
-    case 5: gram_item<5>(a, ii, item); break;
-    case 6: gram_item<6>(a, ii, item); break;
-    case 7: gram_item<7>(a, ii, item); break;
-    default: gram_item<8>(a, ii, item); break;
+  const long long item = (bid - b0) * NT + threadIdx.x;
+  const QItem it = a.dit[ii];
+  switch (it.R) {   // uniform per workgroup
+    case 1: gram_work<1>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 2: gram_work<2>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 3: gram_work<3>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 4: gram_work<4>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 5: gram_work<5>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 6: gram_work<6>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 7: gram_work<7>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    default: gram_work<8>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
   }
 }
 
@@ -1087,12 +1073,12 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       const double* up = a.Upart + (long long)j * a.Rprod + col;
       const long long stride = (long long)Ik * a.Rprod;
       int q = c;
-      for (; q + 7 * nch < a.S; q += 8 * nch) {
-        double x[8];
+      for (; q + 15 * nch < a.S; q += 16 * nch) {
+        double x[16];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) x[u] = up[(long long)(q + u * nch) * stride];
+        for (int u = 0; u < 16; ++u) x[u] = up[(long long)(q + u * nch) * stride];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) v += x[u];
+        for (int u = 0; u < 16; ++u) v += x[u];
       }
       for (; q < a.S; q += nch) v += up[(long long)q * stride];
     }
@@ -1115,34 +1101,54 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   for (int t = 0; t < a.nsub; ++t) {
     const SubBlock& B = a.sb[t];
     const int R = B.R, np = B.np;
-    // H_j partials over d-tiles (thread (p, c) sums d = c mod cpp) and, in the
-    // same phase, b_j partials (thread (r_i, c) sums the other U indices)
+    // far-side factor G_{i,k}(:, y) for this thread's edge-refresh entries,
+    // issued now so that it has arrived when the new column is known
+    const double* Gik = G + B.goff_ik;
+    double gpre[MAXR];
+    {
+      const int y = min(tid, B.Ii - 1);
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) gpre[r] = r < R ? Gik[(long long)r * B.Ii + y] : 0.0;
+    }
+    // H_j partials: thread (p, c) sums d = c mod cpp.  Per d-tile, the
+    // weights w_j(d) = prod_{m in d} W_{k,m}(j, i_m)^2 are formed once in LDS;
+    // the first Q entries of the tile are requested before that, so the two
+    // latencies overlap.
     const int cpp = NT / np;
     const int p_me = tid % np, c_me = tid / np;
     double hacc = 0.0;
     for (long long d0 = 0; d0 < B.D; d0 += TD) {
       const int nd_t = (int)min((long long)TD, B.D - d0);
+      const double* qp = B.Q + d0 * np + p_me;
+      double qv[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) qv[u] = qp[(long long)min(c_me + u * cpp, nd_t - 1) * np];
       for (int e = tid; e < nd_t; e += NT) {
-        long long x = d0 + e;
+        int x = (int)(d0 + e);
         double w = 1.0;
         for (int c = B.nd - 1; c >= 0; --c) {
-          const int im = (int)(x % B.ddim[c]);
-          x /= B.ddim[c];
-          const double v = rows[a.rowoff[B.dt[c]] + im];
+          const int dim = B.ddim[c];
+          const int xq = x / dim;
+          const double v = rows[a.rowoff[B.dt[c]] + (x - xq * dim)];
+          x = xq;
           w *= v * v;
         }
         wl[e] = w;
       }
       __syncthreads();
       if (c_me < cpp) {
-        const double* qp = B.Q + d0 * np + p_me;
-        int e = c_me;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int e = c_me + u * cpp;
+          if (e < nd_t) hacc += wl[e] * qv[u];
+        }
+        int e = c_me + 8 * cpp;
         for (; e + 7 * cpp < nd_t; e += 8 * cpp) {
-          double qv[8];
+          double q2[8];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) qv[u] = qp[(long long)(e + u * cpp) * np];
+          for (int u = 0; u < 8; ++u) q2[u] = qp[(long long)(e + u * cpp) * np];
 #pragma unroll
-          for (int u = 0; u < 8; ++u) hacc += wl[e + u * cpp] * qv[u];
+          for (int u = 0; u < 8; ++u) hacc += wl[e + u * cpp] * q2[u];
         }
         for (; e < nd_t; e += cpp) hacc += wl[e] * qp[(long long)e * np];
       }
@@ -1206,11 +1212,10 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
     __syncthreads();
 
     // row j of W_{k,i} from the new column: LDS copy for the next i, HBM for later blocks
-    const double* Gik = G + B.goff_ik;
     for (int y = tid; y < B.Ii; y += NT) {
       double gv[MAXR];
 #pragma unroll
-      for (int r = 0; r < MAXR; ++r) gv[r] = r < R ? Gik[(long long)r * B.Ii + y] : 0.0;
+      for (int r = 0; r < MAXR; ++r) gv[r] = y < NT ? gpre[r] : (r < R ? Gik[(long long)r * B.Ii + y] : 0.0);
       double sum = 0.0;
 #pragma unroll
       for (int r = 0; r < MAXR; ++r)
