@@ -34,7 +34,44 @@ def parse():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=0, help="oracle sweeps (0 = auto, ~10-30 s)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run 5 plain device copies of MIB MiB (scale for the HBM byte counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_msi256_traffic.txt")
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per contraction launch from the committed counter summary, or None.
+
+    The summary holds FETCH_SIZE and WRITE_SIZE per dispatch, already scaled by
+    a plain copy of known size; it counts only while the kernel sources are the
+    ones the counters were taken on."""
+    if workload != "msi256" or precision != "fp32" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    rec = {}
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            if line.startswith("bench:"):
+                for kv in line.split()[1:]:
+                    k, _, v = kv.partition("=")
+                    rec[k] = v
+    from paper_2511_16358_amd.profsum import kernel_source_digest
+    if rec.get("kernel_sources_sha256") != kernel_source_digest():
+        return None
+    return float(rec["hbm_bytes_per_launch"])
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.rand(n, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(5):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_each_way": n * 4, "copies": 5}), flush=True)
 
 
 def algorithmic_bytes(dims, esz, mask_frac):
@@ -90,10 +127,13 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     from paper_2511_16358_amd import ifctn
     from paper_2511_16358_amd import workloads as W
 
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
     prec = ifctn.IFCTN_FP64 if args.precision == "fp64" else ifctn.IFCTN_FP32
     esz = 8 if prec == ifctn.IFCTN_FP64 else 4
 
@@ -142,8 +182,11 @@ def main():
     con_bytes = n_con * rd + n_fused * upd
     dominant = max(per, key=lambda k: per[k]["total_ms"])
     con_gbs = con_bytes / (per["contract"]["total_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(args.workload, args.precision)
     roof = {"bound": "hbm", "achieved": round(con_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(con_gbs / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(con_gbs / HBM_PEAK_GBS, 4),
+            "traffic": None if traffic is None else round(traffic),
+            "algorithmic_bytes_per_launch": round(con_bytes / max(n_con, 1)),
             "kernel": "k_contract (mode-k contraction, fused X step on mode 0)",
             "avg_us": round(per["contract"]["avg_us"], 2)}
 

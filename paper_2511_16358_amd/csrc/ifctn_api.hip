@@ -570,11 +570,16 @@ hipError_t timed(ifctn_job* J, int cls, hipError_t (*fn)(ifctn_job*, const void*
     if (err != hipSuccess) return err;
     v.push_back(e);
   }
-  hipError_t err = hipEventRecord(v[2 * n], J->stream);
+  // the launch itself stamps the pair with the kernel's start and end
+  set_kernel_events(v[2 * n], v[2 * n + 1]);
+  hipError_t err = fn(J, ctx);
+  const bool used = kernel_events_used();
+  set_kernel_events(nullptr, nullptr);
   if (err != hipSuccess) return err;
-  err = fn(J, ctx);
-  if (err != hipSuccess) return err;
-  err = hipEventRecord(v[2 * n + 1], J->stream);
+  if (!used) {  // nothing was launched: an empty interval
+    err = hipEventRecord(v[2 * n], J->stream);
+    if (err == hipSuccess) err = hipEventRecord(v[2 * n + 1], J->stream);
+  }
   J->evn[cls] = n + 1;
   return err;
 }

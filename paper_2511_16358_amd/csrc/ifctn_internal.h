@@ -150,6 +150,9 @@ hipError_t launch_contract(int dtype, bool upd, bool con, int spt, const Contrac
                            size_t smem, hipStream_t s);
 size_t contract_smem_bytes(int dtype, const ContractArgs& a);
 hipError_t launch_q(const QArgs& a, hipStream_t s);
+// events stamped with the next hot-path kernel's start and end (nullptr = off)
+void set_kernel_events(hipEvent_t start, hipEvent_t stop);
+bool kernel_events_used();
 hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s);
 size_t solve_smem_bytes(const SolveArgs& a);
 hipError_t launch_reconstruct(int dtype, const ReconArgs& a, hipStream_t s);

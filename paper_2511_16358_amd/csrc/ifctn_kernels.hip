@@ -12,6 +12,7 @@
 // Reductions are fixed-order (no floating-point atomics), so every launch is
 // bitwise reproducible.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <algorithm>
 #include <cstdint>
@@ -1299,6 +1300,32 @@ hipError_t launch_edge(int dtype, const double* Gab, const double* Gba, int R, i
   return hipGetLastError();
 }
 
+// Per-launch timing: when events are set, the hot-path launchers go through
+// hipExtLaunchKernel, which stamps the events with the kernel's own start and
+// end, so the measured time is the kernel's execution alone.
+namespace {
+thread_local hipEvent_t tl_ev_start = nullptr, tl_ev_stop = nullptr;
+thread_local bool tl_ev_used = false;
+}  // namespace
+
+void set_kernel_events(hipEvent_t start, hipEvent_t stop) {
+  tl_ev_start = start;
+  tl_ev_stop = stop;
+  tl_ev_used = false;
+}
+
+bool kernel_events_used() { return tl_ev_used; }
+
+#define IFCTN_GO(kern, grid, blk, smem, s, ...)                                                   \
+  do {                                                                                            \
+    if (tl_ev_start) {                                                                            \
+      hipExtLaunchKernelGGL(kern, grid, blk, smem, s, tl_ev_start, tl_ev_stop, 0u, __VA_ARGS__);  \
+      tl_ev_used = true;                                                                          \
+    } else {                                                                                      \
+      hipLaunchKernelGGL(kern, grid, blk, smem, s, __VA_ARGS__);                                  \
+    }                                                                                             \
+  } while (0)
+
 size_t contract_smem_bytes(int dtype, const ContractArgs& a) {
   if (a.kind != 0) return flayout(dtype == 0 ? 4 : 8, a).total;
   return clayout(dtype == 0 ? 4 : 8, a).total;
@@ -1310,7 +1337,7 @@ static hipError_t contract_dispatch(bool upd, bool con, int spt, const ContractA
   const dim3 grid((unsigned)(a.JT * a.S)), blk(NT);
 #define IFCTN_CASE(U, C, P)                                                      \
   if (upd == U && con == C && spt == P) {                                        \
-    hipLaunchKernelGGL((k_contract<TX, TC, U, C, P>), grid, blk, smem, s, a);    \
+    IFCTN_GO((k_contract<TX, TC, U, C, P>), grid, blk, smem, s, a);             \
     return hipGetLastError();                                                    \
   }
   IFCTN_CASE(true, false, 1)
@@ -1328,7 +1355,7 @@ static hipError_t fast_dispatch_nc(bool upd, bool con, int spt, const ContractAr
   if (a.kind == 1) {
 #define IFCTN_ROWS(U, C, P)                                                              \
   if (upd == U && con == C && spt == P) {                                                \
-    hipLaunchKernelGGL((k_contract_rows<TX, TC, NC, U, C, P>), grid, blk, smem, s, a);   \
+    IFCTN_GO((k_contract_rows<TX, TC, NC, U, C, P>), grid, blk, smem, s, a);             \
     return hipGetLastError();                                                            \
   }
     IFCTN_ROWS(true, false, 1)
@@ -1338,7 +1365,7 @@ static hipError_t fast_dispatch_nc(bool upd, bool con, int spt, const ContractAr
   } else if (a.kind == 2 && con && !upd) {
 #define IFCTN_COLS(P)                                                              \
   if (spt == P) {                                                                  \
-    hipLaunchKernelGGL((k_contract_cols<TX, TC, NC, P>), grid, blk, smem, s, a);   \
+    IFCTN_GO((k_contract_cols<TX, TC, NC, P>), grid, blk, smem, s, a);             \
     return hipGetLastError();                                                      \
   }
     IFCTN_COLS(1) IFCTN_COLS(2) IFCTN_COLS(4) IFCTN_COLS(8)
@@ -1369,7 +1396,7 @@ hipError_t launch_contract(int dtype, bool upd, bool con, int spt, const Contrac
 
 hipError_t launch_q(const QArgs& a, hipStream_t s) {
   if (a.blk0[a.ni] == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_gram_q, dim3((unsigned)a.blk0[a.ni]), dim3(NT), 0, s, a);
+  IFCTN_GO(k_gram_q, dim3((unsigned)a.blk0[a.ni]), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1381,9 +1408,9 @@ size_t solve_smem_bytes(const SolveArgs& a) {
 hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s) {
   const size_t smem = solve_smem_bytes(a);
   if (dtype == 0)
-    hipLaunchKernelGGL(k_solve<float>, dim3((unsigned)a.Ik), dim3(NT), smem, s, a);
+    IFCTN_GO(k_solve<float>, dim3((unsigned)a.Ik), dim3(NT), smem, s, a);
   else
-    hipLaunchKernelGGL(k_solve<double>, dim3((unsigned)a.Ik), dim3(NT), smem, s, a);
+    IFCTN_GO(k_solve<double>, dim3((unsigned)a.Ik), dim3(NT), smem, s, a);
   return hipGetLastError();
 }
 
