@@ -31,7 +31,10 @@ def parse():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="msi256")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"],
+                    help="bf16 = bfloat16 X streaming + float32 refinement sweeps (BF16_REFINE)")
+    ap.add_argument("--refine", type=int, default=30, help="float32 refinement sweeps of the bf16 path")
+    ap.add_argument("--no-compare", action="store_true", help="skip the bf16-vs-fp32 equal-RSE comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=0, help="oracle sweeps (0 = auto, ~10-30 s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -119,6 +122,48 @@ def cpu_baseline(name, seed, sweeps_req):
                       f"single thread, {dt:.1f} s"}
 
 
+def timed_run(ifctn, torch, p, precision, steps, warmup, refine=0):
+    """Warm-up, then `steps` sweeps timed with events on the job's stream
+    (the last `refine` of them after promotion for the bf16 path).
+    Returns (ms, RSE, job)."""
+    job = ifctn.Job(p.O, p.mask, p.G0, p.dims, p.ranks, rho=p.rho, precision=precision)
+    stream = torch.cuda.current_stream()
+    if warmup:
+        # warm-up on a scratch job so the timed job starts from X^0
+        wj = ifctn.Job(p.O, p.mask, p.G0, p.dims, p.ranks, rho=p.rho, precision=precision)
+        wj.sweep(warmup, stats=True)
+        wj.close()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    if precision == ifctn.IFCTN_BF16_REFINE:
+        job.sweep(steps - refine, stats=False)
+        job.promote()
+        job.sweep(refine, stats=False)
+    else:
+        job.sweep(steps, stats=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    X = job.x().cpu().numpy().astype(np.float64)
+    rse = float(np.linalg.norm((X - p.X_true).ravel()) / np.linalg.norm(p.X_true.astype(np.float64).ravel()))
+    return ev0.elapsed_time(ev1), rse, job
+
+
+def precision_comparison(ifctn, torch, p, steps, refine):
+    """Equal-RSE comparison: the FP32 path and the bf16 path (steps - refine
+    bfloat16 sweeps + refine float32 sweeps) over the same sweep count."""
+    ms32, rse32, j = timed_run(ifctn, torch, p, ifctn.IFCTN_FP32, steps, 3)
+    j.close()
+    msb, rseb, j = timed_run(ifctn, torch, p, ifctn.IFCTN_BF16_REFINE, steps, 3, refine)
+    j.close()
+    return {"sweeps": steps,
+            "fp32": {"sweeps_per_s": round(steps / (ms32 / 1e3), 2), "rse": rse32},
+            "bf16_refine": {"sweeps_per_s": round(steps / (msb / 1e3), 2), "rse": rseb,
+                            "bf16_sweeps": steps - refine, "fp32_refine_sweeps": refine},
+            "equal_rse": bool(rseb <= 1.01 * rse32),
+            "speedup_bf16_over_fp32": round(ms32 / msb, 4)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -134,8 +179,8 @@ def main():
     from paper_2511_16358_amd import ifctn
     from paper_2511_16358_amd import workloads as W
 
-    prec = ifctn.IFCTN_FP64 if args.precision == "fp64" else ifctn.IFCTN_FP32
-    esz = 8 if prec == ifctn.IFCTN_FP64 else 4
+    prec = {"fp32": ifctn.IFCTN_FP32, "fp64": ifctn.IFCTN_FP64, "bf16": ifctn.IFCTN_BF16_REFINE}[args.precision]
+    esz = {"fp32": 4, "fp64": 8, "bf16": 2}[args.precision]
 
     # synthetic input: planted part assembled by the library itself
     d = W.draw(args.workload, 0)
@@ -194,6 +239,10 @@ def main():
     rse = float(np.linalg.norm((Xf - p.X_true).ravel()) / np.linalg.norm(p.X_true.astype(np.float64).ravel()))
     job.close()
 
+    cmp = None
+    if not args.no_compare and args.precision != "fp64":
+        cmp = precision_comparison(ifctn, torch, p, W.CONFIGS[args.workload][2], args.refine)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, 0, args.cpu_sweeps)
@@ -209,14 +258,16 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if prec == ifctn.IFCTN_FP32 else "f64",
+        "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {W.DESCRIPTIONS[args.workload]}",
                    "dims": list(p.dims), "rank": int(p.ranks[0][1]), "rho": p.rho,
-                   "precision": f"{args.precision} streaming, fp64 Gram/Cholesky/factors/reductions",
+                   "precision": f"{args.precision} X streaming ({'float64' if args.precision == 'fp64' else 'float32'} arithmetic), "
+                                "fp64 Gram/LDL^T/factors/reductions",
                    "parallelism": "single GPU"},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "precision_comparison": cmp,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per.items()},
         "dominant_kernel_class": dominant,
         "rse_after_timed_sweeps": rse,

@@ -55,7 +55,10 @@ typedef enum {
 typedef enum {
   IFCTN_FP32 = 0,        /* X and the streaming passes in float32; Gram, Cholesky,
                             factors and reductions in float64                      */
-  IFCTN_BF16_REFINE = 1, /* reserved: bfloat16 streaming passes + float32 refinement */
+  IFCTN_BF16_REFINE = 1, /* X stored and streamed as bfloat16 (round to nearest even)
+                            with float32 arithmetic, until ifctn_promote (or the last
+                            refine_sweeps sweeps of ifctn_complete) switches the job to
+                            the FP32 path; O, outputs and Xhat are float32            */
   IFCTN_FP64 = 2         /* every step in float64                                   */
 } ifctn_precision;
 
@@ -66,7 +69,8 @@ typedef struct {
   double rho;    /* proximal weight of the factor blocks, > 0 (Sec. 4.2; 0.1 in Sec. 5) */
   double rho_x;  /* proximal weight of the X step, > 0 (eq. (updateX)); 0 => rho      */
   int32_t precision;     /* ifctn_precision                                          */
-  int32_t refine_sweeps; /* reserved, must be 0                                      */
+  int32_t refine_sweeps; /* BF16_REFINE: float32 sweeps that end ifctn_complete (>= 0);
+                            other precisions: must be 0                             */
 } ifctn_params;
 
 typedef struct {
@@ -92,8 +96,8 @@ size_t ifctn_workspace_bytes(const ifctn_params* params);
 /* Create a job: validates params, allocates device memory, sets
  * X^0 = P_Omega(O) (O on Omega, 0 elsewhere; Algorithm 1 initialisation)
  * and G^0 from G0_host.
- *   O_dev:    observed tensor, prod(dims) elements, float32 (FP32 precision) or
- *             float64 (FP64 precision).  Entries off Omega are ignored.
+ *   O_dev:    observed tensor, prod(dims) elements, float32 (FP32 and BF16_REFINE
+ *             precision) or float64 (FP64 precision).  Entries off Omega are ignored.
  *   mask_dev: prod(dims) bytes, nonzero = observed (the sample set Omega).
  *   G0_host:  packed initial factors (float64), required (Algorithm 1 leaves
  *             G^0 to the caller).
@@ -107,19 +111,31 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
  * and fills *stats for the last sweep run. */
 ifctn_status ifctn_sweep(ifctn_job* job, int32_t nsweeps, ifctn_stats* stats);
 
-/* Write a dense tensor to out_dev (float32 for FP32 jobs, float64 for FP64):
- * which = 0: iFCTN(G) of the current factors (eq. (iFCTN)); which = 1: X. */
+/* Write a dense tensor to out_dev (float32 for FP32 and BF16_REFINE jobs,
+ * float64 for FP64): which = 0: iFCTN(G) of the current factors (eq. (iFCTN));
+ * which = 1: X (during the bfloat16 phase: O on Omega, the widened bfloat16
+ * values elsewhere). */
 ifctn_status ifctn_reconstruct(ifctn_job* job, void* out_dev, int32_t which);
 
 /* Copy the current factors to a packed float64 host array.  Synchronises. */
 ifctn_status ifctn_get_factors(ifctn_job* job, double* G_host);
+
+/* End the bfloat16 phase of a BF16_REFINE job (precision pattern: cheap
+ * bfloat16 sweeps, then float32 refinement sweeps of the same PAM iteration,
+ * Algorithm 1): X becomes float32, exactly O on Omega and the widened
+ * bfloat16 values elsewhere, and every later sweep runs the FP32 path.
+ * Idempotent; IFCTN_E_STATE for jobs of other precisions.  Asynchronous. */
+ifctn_status ifctn_promote(ifctn_job* job);
 
 /* Release a job and its device memory (NULL is accepted). */
 ifctn_status ifctn_destroy(ifctn_job* job);
 
 /* Algorithm 1 end to end: init, sweeps until rel_change < eps or t_max sweeps
  * (eps = 0 runs exactly t_max), write X to X_out_dev (same dtype as O_dev),
- * fill *stats (nullable), destroy.  Synchronises. */
+ * fill *stats (nullable), destroy.  Synchronises.  BF16_REFINE: the first
+ * t_max - refine_sweeps sweeps (or fewer, when the stop test is met) stream
+ * bfloat16, then the job is promoted and min(refine_sweeps, t_max) float32
+ * sweeps follow; converged reports the stop test of the bfloat16 phase. */
 ifctn_status ifctn_complete(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
                             const double* G0_host, int32_t t_max, double eps, void* X_out_dev,
                             ifctn_stats* stats, void* stream);

@@ -11,11 +11,12 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libifctn.so")
-SOURCES = ["ifctn_api.hip", "ifctn_kernels.hip"]
+SOURCES = ["ifctn_api.hip", "ifctn_kernels.hip", "ifctn_contract_f32.hip", "ifctn_contract_f64.hip",
+           "ifctn_contract_bf16.hip"]
 
 # Packed-FP32 VALU ops are disabled for all device code (-packed-fp32-ops).
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-mcode-object-version=5", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-mcode-object-version=5", "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
@@ -29,16 +30,34 @@ def hipcc() -> str:
 
 
 def build(verbose: bool = False) -> str:
-    """Compile every HIP source into paper_2511_16358_amd/libifctn.so."""
-    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    """Compile every HIP source (in parallel) and link paper_2511_16358_amd/libifctn.so."""
+    cc = hipcc()
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    procs = []
+    for src in SOURCES:
+        obj = os.path.join(objdir, src.replace(".hip", ".o"))
+        cmd = [cc] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC, "-c", "-o", obj, os.path.join(CSRC, src)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append((src, obj, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)))
+    objs, failed = [], []
+    for src, obj, pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            sys.stderr.write(out)
+            failed.append(src)
+        objs.append(obj)
+    if failed:
+        raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
-    cmd = [hipcc()] + HIPCC_FLAGS + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + srcs
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed building libifctn.so")
+        raise RuntimeError("linking libifctn.so failed")
     os.replace(tmp, LIB)
     return LIB
 

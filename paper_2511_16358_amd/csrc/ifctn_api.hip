@@ -48,8 +48,10 @@ struct Geo {
   long long strides[MAXN] = {};
   long long nX = 0;
   int R[MAXN][MAXN] = {};
-  int dtype = 0;       // 0 float32, 1 float64
+  int dtype = 0;       // streaming arithmetic and master X: 0 float32, 1 float64
   size_t esz = 4;
+  bool bf16 = false;   // BF16_REFINE: X streamed as bfloat16 until the job is promoted
+  int refine = 0;      // float32 sweeps that end ifctn_complete in BF16_REFINE mode
   double rho = 0.1, rho_x = 0.1;
   long long goff[MAXN][MAXN] = {};
   long long nG = 0;
@@ -66,10 +68,10 @@ ifctn_status make_geo(const ifctn_params* p, Geo* g) {
   if (N < 2 || N > IFCTN_MAX_ORDER) return fail(IFCTN_E_INVAL, "order %d outside 2..%d", N, IFCTN_MAX_ORDER);
   if (!(p->rho > 0.0) || !std::isfinite(p->rho)) return fail(IFCTN_E_INVAL, "rho must be > 0");
   if (p->rho_x < 0.0 || !std::isfinite(p->rho_x)) return fail(IFCTN_E_INVAL, "rho_x must be >= 0 (0 = rho)");
-  if (p->precision == IFCTN_BF16_REFINE) return fail(IFCTN_E_UNSUPPORTED, "BF16_REFINE precision is not built");
-  if (p->precision != IFCTN_FP32 && p->precision != IFCTN_FP64)
+  if (p->precision != IFCTN_FP32 && p->precision != IFCTN_FP64 && p->precision != IFCTN_BF16_REFINE)
     return fail(IFCTN_E_INVAL, "unknown precision %d", p->precision);
-  if (p->refine_sweeps != 0) return fail(IFCTN_E_INVAL, "refine_sweeps must be 0");
+  if (p->precision == IFCTN_BF16_REFINE ? p->refine_sweeps < 0 : p->refine_sweeps != 0)
+    return fail(IFCTN_E_INVAL, "refine_sweeps must be >= 0 for BF16_REFINE and 0 otherwise");
   g->N = N;
   long long nX = 1;
   for (int m = 0; m < N; ++m) {
@@ -96,6 +98,8 @@ ifctn_status make_geo(const ifctn_params* p, Geo* g) {
     }
   g->dtype = p->precision == IFCTN_FP64 ? 1 : 0;
   g->esz = g->dtype ? 8 : 4;
+  g->bf16 = p->precision == IFCTN_BF16_REFINE;
+  g->refine = g->bf16 ? p->refine_sweeps : 0;
   g->rho = p->rho;
   g->rho_x = p->rho_x > 0.0 ? p->rho_x : p->rho;
   long long off = 0;
@@ -411,7 +415,9 @@ struct ifctn_job {
   hipStream_t stream = nullptr;
   unsigned char* arena = nullptr;
   size_t arena_bytes = 0;
-  void* X = nullptr;
+  void* X = nullptr;          // master X (float32 / float64)
+  bf16x* Xb = nullptr;        // bfloat16 X of the BF16 phase (BF16_REFINE jobs)
+  bool bf16_phase = false;
   uint32_t* bits = nullptr;
   double* G = nullptr;
   double* W64 = nullptr;
@@ -437,7 +443,7 @@ struct ifctn_job {
 namespace {
 
 struct Sizes {
-  size_t x, bits, G, W64, Wc, Q, Upart, Ufin, normpart, dgpart, stats, flag, qitems, total;
+  size_t x, xb, bits, G, W64, Wc, Q, Upart, Ufin, normpart, dgpart, stats, flag, qitems, total;
 };
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
@@ -445,6 +451,7 @@ size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
   Sizes s;
   s.x = al256(g.nX * g.esz);
+  s.xb = g.bf16 ? al256(g.nX * 2) : 0;
   s.bits = al256(((g.nX + 63) / 64) * 8);
   s.G = al256(g.nG * 8);
   s.W64 = al256(g.nW * 8);
@@ -481,7 +488,7 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
   s.stats = al256(8 * 8);
   s.flag = al256(16);
   s.qitems = al256(sizeof(QItem) * MAXN * (MAXN - 1));
-  s.total = s.x + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.normpart + s.dgpart + s.stats + s.flag +
+  s.total = s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.normpart + s.dgpart + s.stats + s.flag +
             s.qitems;
   return s;
 }
@@ -592,7 +599,8 @@ struct ContractCall {
 hipError_t do_contract(ifctn_job* J, const void* c) {
   const ContractCall* cc = (const ContractCall*)c;
   const ContractPlan& P = J->cplan[cc->k];
-  return launch_contract(J->g.dtype, cc->upd, cc->con, cc->con ? P.spt : 1, P.a, P.smem, J->stream);
+  const int kt = J->bf16_phase ? KT_BF16 : (J->g.dtype ? KT_F64 : KT_F32);
+  return launch_contract(kt, cc->upd, cc->con, cc->con ? P.spt : 1, P.a, P.smem, J->stream);
 }
 
 hipError_t do_gram(ifctn_job* J, const void* c) { return launch_q(*(const QArgs*)c, J->stream); }
@@ -625,6 +633,19 @@ hipError_t flush_update(ifctn_job* J) {
   hipError_t e = timed(J, KC_UPDATE, do_contract, &cc);
   J->pending = false;
   return e;
+}
+
+// End the bfloat16 phase: the float32 master takes the widened bf16 values off
+// Omega (it holds O on Omega), and every later pass streams float32.
+hipError_t promote(ifctn_job* J) {
+  if (!J->bf16_phase) return hipSuccess;
+  hipError_t e = flush_update(J);
+  if (e != hipSuccess) return e;
+  e = launch_widen(J->Xb, J->bits, (const float*)J->X, (float*)J->X, J->g.nX, J->stream);
+  if (e != hipSuccess) return e;
+  J->bf16_phase = false;
+  for (int k = 0; k < J->g.N; ++k) J->cplan[k].a.X = J->X;
+  return hipSuccess;
 }
 
 }  // namespace
@@ -695,6 +716,7 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
   J->arena_bytes = s.total;
   unsigned char* p = J->arena;
   J->X = p;                      p += s.x;
+  J->Xb = (bf16x*)p;             p += s.xb;
   J->bits = (uint32_t*)p;        p += s.bits;
   J->G = (double*)p;             p += s.G;
   J->W64 = (double*)p;           p += s.W64;
@@ -707,9 +729,10 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
   J->stats5 = (double*)p;        p += s.stats;
   J->flag = (int*)p;             p += s.flag;
   QItem* dq = (QItem*)p;         p += s.qitems;
+  J->bf16_phase = g.bf16;
   for (int k = 0; k < g.N; ++k) {
     ContractArgs& a = J->cplan[k].a;
-    a.X = J->X;
+    a.X = g.bf16 ? (void*)J->Xb : J->X;
     a.maskbits = J->bits;
     a.Wc = J->Wc;
     a.G = J->G;
@@ -747,6 +770,7 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
     INIT_TRY(hipMemcpyAsync((void*)J->qplan[k].dit, J->qplan[k].it, sizeof(QItem) * (MAXN - 1),
                             hipMemcpyHostToDevice, J->stream));
   INIT_TRY(launch_init_x(g.dtype, O_dev, mask_dev, J->X, J->bits, J->flag, g.nX, J->stream));
+  if (g.bf16) INIT_TRY(launch_narrow((const float*)J->X, J->Xb, g.nX, J->stream));
   for (int e2 = 0; e2 < g.ne; ++e2) {
     const int a = g.ea[e2], b = g.eb[e2];
     INIT_TRY(launch_edge(g.dtype, J->G + g.goff[a][b], J->G + g.goff[b][a], g.R[a][b], g.dims[a], g.dims[b],
@@ -789,7 +813,10 @@ ifctn_status ifctn_reconstruct(ifctn_job* J, void* out_dev, int32_t which) {
   if (!J || !out_dev) return fail(IFCTN_E_INVAL, "job and out_dev are required");
   if (which == 1) {
     HIPTRY(flush_update(J));
-    HIPTRY(hipMemcpyAsync(out_dev, J->X, J->g.nX * J->g.esz, hipMemcpyDeviceToDevice, J->stream));
+    if (J->bf16_phase)
+      HIPTRY(launch_widen(J->Xb, J->bits, (const float*)J->X, (float*)out_dev, J->g.nX, J->stream));
+    else
+      HIPTRY(hipMemcpyAsync(out_dev, J->X, J->g.nX * J->g.esz, hipMemcpyDeviceToDevice, J->stream));
     return IFCTN_OK;
   }
   if (which != 0) return fail(IFCTN_E_INVAL, "which must be 0 or 1");
@@ -817,6 +844,13 @@ ifctn_status ifctn_get_factors(ifctn_job* J, double* G_host) {
   return IFCTN_OK;
 }
 
+ifctn_status ifctn_promote(ifctn_job* J) {
+  if (!J) return fail(IFCTN_E_INVAL, "job is NULL");
+  if (!J->g.bf16) return fail(IFCTN_E_STATE, "ifctn_promote needs a BF16_REFINE job");
+  HIPTRY(promote(J));
+  return IFCTN_OK;
+}
+
 ifctn_status ifctn_complete(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
                             const double* G0_host, int32_t t_max, double eps, void* X_out_dev,
                             ifctn_stats* stats, void* stream) {
@@ -828,18 +862,28 @@ ifctn_status ifctn_complete(const ifctn_params* params, const void* O_dev, const
   if (st != IFCTN_OK) return st;
   ifctn_stats s;
   std::memset(&s, 0, sizeof(s));
+  // BF16_REFINE: the last `refine` sweeps stream float32 (after promotion)
+  const int refine = std::min(J->g.refine, t_max);
+  const int t_main = t_max - refine;
+  int converged = 0;
   if (eps == 0.0) {
-    st = ifctn_sweep(J, t_max, &s);
+    if (t_main > 0) st = ifctn_sweep(J, t_main, &s);
   } else {
-    for (int t = 0; t < t_max; ++t) {
+    for (int t = 0; t < t_main; ++t) {
       st = ifctn_sweep(J, 1, &s);
       if (st != IFCTN_OK) break;
       if (s.rel_change < eps) {
-        s.converged = 1;
+        converged = 1;
         break;
       }
     }
   }
+  if (st == IFCTN_OK && J->g.bf16) {
+    hipError_t e = promote(J);
+    if (e != hipSuccess) st = fail(IFCTN_E_HIP, "promote: %s", hipGetErrorString(e));
+    if (st == IFCTN_OK && refine > 0) st = ifctn_sweep(J, refine, &s);
+  }
+  s.converged = converged;
   if (st == IFCTN_OK) st = ifctn_reconstruct(J, X_out_dev, 1);
   if (st == IFCTN_OK) {
     hipError_t e = hipStreamSynchronize(J->stream);

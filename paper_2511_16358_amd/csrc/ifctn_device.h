@@ -1,0 +1,872 @@
+// Device code shared by the translation units of libifctn.so: small helpers,
+// the mode-k contraction kernels (templates over the X storage type and the
+// streaming arithmetic type) and their launch dispatch.  Each contraction
+// translation unit instantiates one type pair, so the library compiles in
+// parallel.
+#pragma once
+
+#include <hip/hip_ext.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "ifctn_internal.h"
+
+namespace ifctn {
+
+
+// --------------------------------------------------------------------------
+// small helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+  // fixed butterfly order: every run adds the same operands in the same order
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T ld(const T* p, long long i) {
+  return p[i];
+}
+
+__device__ __forceinline__ long long eaddr(const EdgeRef e, long long a, long long b) {
+  return e.off + a * e.s1 + b * e.s2;
+}
+
+// for (e = tid; e < n; e += NT) use(e, load(e)), with the loads of U
+// consecutive iterations issued before any of them is consumed (the index is
+// clamped so that every load is in bounds and the body has no branches)
+template <int U, typename Load, typename Use>
+__device__ __forceinline__ void for_batched(int n, Load load, Use use) {
+  for (int eb = threadIdx.x; eb < n; eb += NT * U) {
+    decltype(load(0)) v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = load(min(eb + u * NT, n - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (eb + u * NT < n) use(eb + u * NT, v[u]);
+  }
+}
+// --------------------------------------------------------------------------
+// K3 (+ K6): mode-k contraction, optionally fused with the X step of the
+// previous sweep.
+//
+// A workgroup owns j-tile [j0, j0+jn) of mode k and a range of planes.  Per
+// batch of PB planes it
+//   (a) decodes the planes, forms S_k's plane-constant part and the
+//       Kronecker coefficients a_c(r_c) = prod_{m in c} G_{m,k}(r_m, i_m),
+//   (b) streams the X elements of the batch from HBM (optionally applying
+//       eq. (updateX) first and writing X back), multiplies by S_k and
+//       stages Y = X * S_k in LDS,
+//   (c) contracts the fibre mode: T(j, r_f) = sum_{i_f} Y(j, i_f) G_{f,k}(r_f, i_f),
+//   (d) accumulates U(j, r_c, r_f) += a_c(r_c) T(j, r_f) into float64
+//       registers; each (j, r) slot is owned by one thread.
+// The Khatri-Rao / Kronecker expansion of Z_k is never materialised.
+// --------------------------------------------------------------------------
+struct CLayout {
+  size_t pbase, pidx, acoef, scc, scf, t0, tile, T, gf, red, total;
+};
+
+__host__ __device__ inline size_t al16(size_t x) { return (x + 15) & ~size_t(15); }
+
+__host__ __device__ inline CLayout clayout(int tcsz, const ContractArgs& a) {
+  CLayout L;
+  size_t o = 0;
+  L.pbase = o; o = al16(o + (size_t)a.PB * 8);
+  L.pidx = o;  o = al16(o + (size_t)a.PB * MAXC * 4);
+  L.acoef = o; o = al16(o + (size_t)a.PB * a.Rc * 8);
+  L.scc = o;   o = al16(o + (size_t)a.PB * tcsz);
+  L.scf = o;   o = al16(o + (size_t)a.PB * a.LDF * tcsz);
+  L.t0 = o;    o = al16(o + (size_t)a.PB * a.jn * tcsz);
+  L.tile = o;  o = al16(o + std::max((size_t)a.PB * a.jn * a.LDF * tcsz, (size_t)NT * 8));
+  L.T = o;     o = al16(o + (size_t)a.PB * a.jn * a.Rf * tcsz);
+  L.gf = o;    o = al16(o + (size_t)a.If * a.Rf * tcsz);
+  L.red = o;   o = al16(o + 4 * 3 * 8);
+  L.total = o;
+  return L;
+}
+
+constexpr int UNR = 8;   // X elements in flight per thread in the streaming stage
+
+template <typename TX, typename TC, bool UPD, bool CON, int SPT>
+__global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const CLayout Ly = clayout((int)sizeof(TC), a);
+  long long* pbase = (long long*)(smem + Ly.pbase);
+  int* pidx = (int*)(smem + Ly.pidx);
+  double* acoef = (double*)(smem + Ly.acoef);
+  TC* sccl = (TC*)(smem + Ly.scc);
+  TC* scf = (TC*)(smem + Ly.scf);
+  TC* t0 = (TC*)(smem + Ly.t0);
+  TC* tile = (TC*)(smem + Ly.tile);
+  TC* Tl = (TC*)(smem + Ly.T);
+  TC* gf = (TC*)(smem + Ly.gf);
+  double* red = (double*)(smem + Ly.red);
+
+  const int bid = (int)blockIdx.x;
+  const int tid = threadIdx.x;
+  const int jt = bid % a.JT;
+  const int sp = bid / a.JT;
+  const int j0 = jt * a.jn;
+  const int jcnt = min(a.jn, a.Ik - j0);
+  const long long p_begin = (long long)sp * a.PPW;
+  const long long p_end = min(a.nplanes, p_begin + a.PPW);
+  const TC* __restrict__ Wc = (const TC*)a.Wc;
+  TX* __restrict__ X = (TX*)a.X;
+  const double* __restrict__ G = a.G;
+  const int If = a.If, Rf = a.Rf, Rc = a.Rc, Rprod = a.Rprod, nc = a.nc, jn = a.jn, LDF = a.LDF;
+  const int psplit = a.psplit;
+
+  // accumulator slots: slot s -> (j, r_c, r_f) and a plane residue class
+  double acc[SPT];
+  int aoff[SPT], toff[SPT], psub[SPT];
+#pragma unroll
+  for (int q = 0; q < SPT; ++q) {
+    acc[q] = 0.0;
+    aoff[q] = -1;
+    toff[q] = 0;
+    psub[q] = 0;
+    if (CON) {
+      const int s = q * NT + tid;
+      if (s < jcnt * Rprod * psplit) {
+        const int b = s / psplit;
+        const int jl = b / Rprod, sl = b - jl * Rprod;
+        psub[q] = s - b * psplit;
+        aoff[q] = sl / Rf;
+        toff[q] = jl * Rf + (sl - (sl / Rf) * Rf);
+      }
+    }
+  }
+  if (CON) {
+    for_batched<4>(
+        Rf * If, [&](int e) { return G[a.gfoff + e]; },
+        [&](int e, double v) {
+          const int r = e / If, ff = e - r * If;
+          gf[ff * Rf + r] = (TC)v;
+        });
+  }
+  double dx2 = 0.0, x2 = 0.0, f2 = 0.0;
+  const TC rx = (TC)a.rho_x;
+  const TC inv1 = (TC)1 / ((TC)1 + rx);
+
+  for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
+    const int np = (int)min((long long)a.PB, p_end - pb0);
+    // (a) planes: base offsets, S_k factors, Kronecker coefficients
+    for (int e = tid; e < np; e += NT) {
+      long long p = pb0 + e, base = 0;
+      int ic[MAXC];
+      for (int c = nc - 1; c >= 0; --c) {
+        ic[c] = (int)(p % a.cdim[c]);
+        p /= a.cdim[c];
+        base += (long long)ic[c] * a.cstride[c];
+      }
+      TC s = (TC)1;
+      for (int q = 0; q < a.ncc; ++q) s *= Wc[eaddr(a.ecc[q], ic[a.cc_a[q]], ic[a.cc_b[q]])];
+      pbase[e] = base;
+      sccl[e] = s;
+      for (int c = 0; c < MAXC; ++c) pidx[e * MAXC + c] = c < nc ? ic[c] : 0;
+    }
+    __syncthreads();
+    for_batched<4>(
+        np * If,
+        [&](int e) {
+          const int pl = e / If, ff = e - pl * If;
+          TC s = sccl[pl];
+#pragma unroll
+          for (int c = 0; c < MAXC; ++c)
+            if (c < nc) s *= Wc[eaddr(a.ecf[c], pidx[pl * MAXC + c], ff)];
+          return s;
+        },
+        [&](int e, TC v) {
+          const int pl = e / If;
+          scf[pl * LDF + (e - pl * If)] = v;
+        });
+    if (CON) {
+      for_batched<4>(
+          np * Rc,
+          [&](int e) {
+            const int pl = e / Rc;
+            int rr = e - pl * Rc;
+            double v = 1.0;
+#pragma unroll
+            for (int c = MAXC - 1; c >= 0; --c) {
+              if (c < nc) {
+                const int r = rr % a.crank[c];
+                rr /= a.crank[c];
+                v *= G[a.gcoff[c] + (long long)r * a.cdim[c] + pidx[pl * MAXC + c]];
+              }
+            }
+            return v;
+          },
+          [&](int e, double v) { acoef[e] = v; });
+    }
+    if (UPD) {
+      for_batched<4>(
+          np * jcnt,
+          [&](int e) {
+            const int pl = e / jcnt, jl = e - pl * jcnt;
+            TC v = (TC)1;
+#pragma unroll
+            for (int c = 0; c < MAXC; ++c)
+              if (c < nc) v *= Wc[eaddr(a.e0c[c], j0 + jl, pidx[pl * MAXC + c])];
+            return v;
+          },
+          [&](int e, TC v) {
+            const int pl = e / jcnt;
+            t0[pl * jn + (e - pl * jcnt)] = v;
+          });
+    }
+    __syncthreads();
+
+    // (b) stream X.  The batch is enumerated over the extents of the axes
+    // ord[0..2] (slowest memory stride first); a carried mixed-radix counter
+    // replaces divisions, and UNR loads are issued before any is consumed.
+    {
+      const int o0 = a.ord[0], o1 = a.ord[1];
+      const int D0 = o0 == 0 ? jcnt : (o0 == 1 ? np : If);
+      const int D1 = o1 == 0 ? jcnt : (o1 == 1 ? np : If);
+      const int D2 = (o0 != 0 && o1 != 0) ? jcnt : ((o0 != 1 && o1 != 1) ? np : If);
+      const int total = D0 * D1 * D2;
+      const int s2 = NT % D2, s1 = (NT / D2) % D1, s0 = NT / (D1 * D2);
+      int i2 = tid % D2, i1 = (tid / D2) % D1, i0 = tid / (D1 * D2);
+      for (int eb = tid; eb < total; eb += NT * UNR) {
+        long long Lv[UNR];
+        int pv[UNR], jv[UNR], fv[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const bool ok = eb + u * NT < total;
+          const int jl = o0 == 0 ? i0 : (o1 == 0 ? i1 : i2);
+          const int pl = o0 == 1 ? i0 : (o1 == 1 ? i1 : i2);
+          const int ff = (o0 != 2 && o1 != 2) ? i2 : (o0 == 2 ? i0 : i1);
+          jv[u] = ok ? jl : 0;
+          pv[u] = ok ? pl : 0;
+          fv[u] = ok ? ff : 0;
+          // out-of-range lanes load element (0, 0, 0) of the batch and drop it
+          Lv[u] = pbase[pv[u]] + (long long)(j0 + jv[u]) * a.stride_k + (long long)fv[u] * a.stride_f;
+          if (!ok) Lv[u] = -1 - Lv[u];
+          i2 += s2;
+          if (i2 >= D2) { i2 -= D2; ++i1; }
+          i1 += s1;
+          if (i1 >= D1) { i1 -= D1; ++i0; }
+          i0 += s0;
+        }
+        TX xr[UNR];
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) xr[u] = X[Lv[u] >= 0 ? Lv[u] : -1 - Lv[u]];
+        uint32_t mw[UNR];
+        TC w0[UNR];
+        if (UPD) {
+#pragma unroll
+          for (int u = 0; u < UNR; ++u) {
+            mw[u] = a.maskbits[(Lv[u] >= 0 ? Lv[u] : -1 - Lv[u]) >> 5];
+            w0[u] = Wc[eaddr(a.e0f, j0 + jv[u], fv[u])];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          if (Lv[u] < 0) continue;
+          TC x = (TC)xr[u];
+          const TC sk = scf[pv[u] * LDF + fv[u]];
+          if (UPD) {
+            const TC xh = sk * t0[pv[u] * jn + jv[u]] * w0[u];
+            const bool obs = (mw[u] >> (Lv[u] & 31)) & 1u;
+            // the new value as stored (rounded to the storage type)
+            const TC xn = obs ? x : (TC)(TX)((xh + rx * x) * inv1);
+            if (!obs) X[Lv[u]] = (TX)xn;
+            const double d = (double)xn - (double)x;
+            dx2 += d * d;
+            x2 += (double)x * (double)x;
+            const double rr = (double)xn - (double)xh;
+            f2 += rr * rr;
+            x = xn;
+          }
+          if (CON) tile[(pv[u] * jn + jv[u]) * LDF + fv[u]] = x * sk;
+        }
+      }
+    }
+    __syncthreads();
+
+    if (CON) {
+      // (c) fibre contraction T(row, r_f), each row shared by fch adjacent lanes
+      const int rows = np * jcnt;
+      const int fch = a.fch;
+      const int rpp = NT / fch;
+      const int chunk = (If + fch - 1) / fch;
+      const int ch = tid & (fch - 1);
+      const int passes = (rows + rpp - 1) / rpp;
+      for (int ps = 0; ps < passes; ++ps) {
+        const int row = ps * rpp + tid / fch;
+        TC t[MAXR];
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) t[r] = (TC)0;
+        if (row < rows) {
+          const int pl = row / jcnt, jl = row - pl * jcnt;
+          const TC* trow = tile + (pl * jn + jl) * LDF;
+          const int lo = ch * chunk, hi = min(If, lo + chunk);
+          for (int ff = lo; ff < hi; ++ff) {
+            const TC v = trow[ff];
+            const TC* g = gf + ff * Rf;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r)
+              if (r < Rf) t[r] += v * g[r];
+          }
+        }
+        for (int o = 1; o < fch; o <<= 1) {
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r) t[r] += __shfl_xor(t[r], o, 64);
+        }
+        if (row < rows && ch == 0) {
+          const int pl = row / jcnt, jl = row - pl * jcnt;
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r)
+            if (r < Rf) Tl[(pl * jn + jl) * Rf + r] = t[r];
+        }
+      }
+      __syncthreads();
+      // (d) Kronecker accumulation into owned slots (planes split round-robin)
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        if (aoff[q] >= 0) {
+          double sum = acc[q];
+          for (int pl = psub[q]; pl < np; pl += psplit)
+            sum += acoef[pl * Rc + aoff[q]] * (double)Tl[pl * jn * Rf + toff[q]];
+          acc[q] = sum;
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if (CON) {
+    // combine the plane residue classes in a fixed order, then write the
+    // slot's canonical U column (modes != k ascending, row-major)
+    double* comb = (double*)(smem + Ly.tile);   // tile is free now; psplit > 1 implies <= NT slots
+    if (psplit > 1) {
+#pragma unroll
+      for (int q = 0; q < SPT; ++q)
+        if (aoff[q] >= 0) comb[q * NT + tid] = acc[q];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      if (aoff[q] >= 0 && psub[q] == 0) {
+        const int s = q * NT + tid;
+        double v = acc[q];
+        for (int t = 1; t < psplit; ++t) v += comb[s + t];
+        const int b = s / psplit;
+        const int jl = b / Rprod, sl = b - jl * Rprod;
+        int rc = sl / Rf;
+        long long col = (long long)(sl - rc * Rf) * a.ustf;
+        for (int c = nc - 1; c >= 0; --c) {
+          const int r = rc % a.crank[c];
+          rc /= a.crank[c];
+          col += (long long)r * a.ustc[c];
+        }
+        a.Upart[((long long)sp * a.Ik + j0 + jl) * Rprod + col] = v;
+      }
+    }
+  }
+  if (UPD) {
+    const double v0 = wave_sum(dx2), v1 = wave_sum(x2), v2 = wave_sum(f2);
+    const int w = tid >> 6;
+    if ((tid & 63) == 0) {
+      red[w * 3 + 0] = v0;
+      red[w * 3 + 1] = v1;
+      red[w * 3 + 2] = v2;
+    }
+    __syncthreads();
+    if (tid < 3) {
+      double sum = 0.0;
+      for (int q = 0; q < NT / 64; ++q) sum += red[q * 3 + tid];
+      a.normpart[(long long)bid * 3 + tid] = sum;
+    }
+  }
+}
+
+// --------------------------------------------------------------------------
+// K3 fast paths.  Same contraction as k_contract, for the two layouts every
+// tensor of this library's workloads uses, with X read from HBM straight into
+// registers (no LDS tile):
+//   rows:    the fibre mode f is the contiguous last mode; each fibre (plane,
+//            j) is split over `fch` adjacent lanes that reduce with a fixed
+//            butterfly;
+//   columns: mode k is the contiguous last mode; lanes run along j (coalesced)
+//            and loop over the fibre, fibre chunks reduced through LDS in a
+//            fixed order.
+// Both finish like k_contract: T(plane, j, r_f) in LDS, then the Kronecker
+// accumulation into float64 slots and the split partials of U_k.
+// --------------------------------------------------------------------------
+struct FLayout {
+  size_t pbase, pidx, acoef, scc, scf, t0, w0f, gf, T, tpart, red, total;
+};
+
+__host__ __device__ inline FLayout flayout(int tcsz, const ContractArgs& a) {
+  FLayout L;
+  size_t o = 0;
+  L.pbase = o; o = al16(o + (size_t)a.PB * 8);
+  L.pidx = o;  o = al16(o + (size_t)a.PB * MAXC * 4);
+  L.acoef = o; o = al16(o + (size_t)a.PB * a.Rc * 8);
+  L.scc = o;   o = al16(o + (size_t)a.PB * tcsz);
+  L.scf = o;   o = al16(o + (size_t)a.PB * a.If * tcsz);
+  L.t0 = o;    o = al16(o + (size_t)a.PB * a.jn * tcsz);
+  L.w0f = o;   o = al16(o + (size_t)(a.k == 0 ? a.jn * a.If : 0) * tcsz);
+  L.gf = o;    o = al16(o + (size_t)a.If * MAXR * tcsz);      // zero-padded to MAXR ranks
+  L.T = o;     o = al16(o + std::max((size_t)a.PB * a.jn * a.Rf * tcsz, (size_t)NT * 8));
+  L.tpart = o; o = al16(o + (a.kind == 2 ? (size_t)NT * a.Rf * tcsz : 0));
+  L.red = o;   o = al16(o + 4 * 3 * 8);
+  L.total = o;
+  return L;
+}
+
+// shared pieces of the fast kernels (NC = number of modes other than k and f,
+// a compile-time constant so that no load sits behind a per-mode branch) -----
+template <typename TC, int NC>
+__device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0, int np, int jcnt, int j0,
+                                            long long* pbase, int* pidx, TC* sccl, TC* scf, double* acoef,
+                                            TC* t0, bool con, bool upd) {
+  const TC* __restrict__ Wc = (const TC*)a.Wc;
+  const int tid = threadIdx.x, If = a.If, Rc = a.Rc, jn = a.jn;
+  for (int e = tid; e < np; e += NT) {
+    long long p = pb0 + e, base = 0;
+    int ic[MAXC > 0 ? MAXC : 1];
+#pragma unroll
+    for (int c = NC - 1; c >= 0; --c) {
+      ic[c] = (int)(p % a.cdim[c]);
+      p /= a.cdim[c];
+      base += (long long)ic[c] * a.cstride[c];
+    }
+    TC sv = (TC)1;
+#pragma unroll
+    for (int x = 0; x < NC; ++x)
+#pragma unroll
+      for (int y = x + 1; y < NC; ++y) sv *= Wc[eaddr(a.ecc[x * (2 * NC - x - 1) / 2 + (y - x - 1)], ic[x], ic[y])];
+    pbase[e] = base;
+    sccl[e] = sv;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) pidx[e * MAXC + c] = ic[c];
+  }
+  __syncthreads();
+  for_batched<4>(
+      np * If,
+      [&](int e) {
+        const int pl = e / If, ff = e - pl * If;
+        TC v = sccl[pl];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) v *= Wc[eaddr(a.ecf[c], pidx[pl * MAXC + c], ff)];
+        return v;
+      },
+      [&](int e, TC v) { scf[e] = v; });
+  if (con) {
+    for_batched<4>(
+        np * Rc,
+        [&](int e) {
+          const int pl = e / Rc;
+          int rr = e - pl * Rc;
+          double v = 1.0;
+#pragma unroll
+          for (int c = NC - 1; c >= 0; --c) {
+            const int r = rr % a.crank[c];
+            rr /= a.crank[c];
+            v *= a.G[a.gcoff[c] + (long long)r * a.cdim[c] + pidx[pl * MAXC + c]];
+          }
+          return v;
+        },
+        [&](int e, double v) { acoef[e] = v; });
+  }
+  if (upd) {
+    for_batched<4>(
+        np * jcnt,
+        [&](int e) {
+          const int pl = e / jcnt, jl = e - pl * jcnt;
+          TC v = (TC)1;
+#pragma unroll
+          for (int c = 0; c < NC; ++c) v *= Wc[eaddr(a.e0c[c], j0 + jl, pidx[pl * MAXC + c])];
+          return v;
+        },
+        [&](int e, TC v) {
+          const int pl = e / jcnt;
+          t0[pl * jn + (e - pl * jcnt)] = v;
+        });
+  }
+  __syncthreads();
+}
+
+// G_{f,k} as gf[f][r] zero-padded to MAXR ranks (unconditional FMAs later)
+template <typename TC>
+__device__ __forceinline__ void load_gf(const ContractArgs& a, TC* gf) {
+  const int If = a.If, Rf = a.Rf;
+  for_batched<4>(
+      If * MAXR,
+      [&](int e) {
+        const int ff = e / MAXR, r = e - ff * MAXR;
+        return r < Rf ? a.G[a.gfoff + (long long)r * If + ff] : 0.0;
+      },
+      [&](int e, double v) { gf[e] = (TC)v; });
+}
+
+template <int SPT>
+struct Slots {
+  double acc[SPT];
+  int aoff[SPT], toff[SPT];
+  int psub;
+  __device__ __forceinline__ void init(int jcnt, int Rprod, int Rf, int psplit) {
+    const int tid = threadIdx.x;
+    psub = tid % psplit;            // NT is a multiple of psplit: the same for every slot
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      acc[q] = 0.0;
+      aoff[q] = -1;
+      toff[q] = 0;
+      const int s = q * NT + tid;
+      if (s < jcnt * Rprod * psplit) {
+        const int b = s / psplit;
+        const int jl = b / Rprod, sl = b - jl * Rprod;
+        aoff[q] = sl / Rf;
+        toff[q] = jl * Rf + (sl - (sl / Rf) * Rf);
+      }
+    }
+  }
+  // planes outer, slots inner: the 2 SPT LDS reads of a plane are issued together
+  template <typename TC>
+  __device__ __forceinline__ void accumulate(const double* acoef, const TC* Tl, int np, int jn, int Rc, int Rf,
+                                             int psplit) {
+    int ao[SPT], to[SPT];
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      ao[q] = aoff[q] >= 0 ? aoff[q] : 0;
+      to[q] = toff[q];
+    }
+    for (int pl = psub; pl < np; pl += psplit) {
+      double av[SPT], tv[SPT];
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) {
+        av[q] = acoef[pl * Rc + ao[q]];
+        tv[q] = (double)Tl[pl * jn * Rf + to[q]];
+      }
+#pragma unroll
+      for (int q = 0; q < SPT; ++q) acc[q] += av[q] * tv[q];
+    }
+  }
+  // combine the plane residue classes in a fixed order and write the slot's
+  // canonical U column (modes != k ascending, row-major)
+  template <int NC>
+  __device__ __forceinline__ void write(const ContractArgs& a, double* comb, int sp, int j0) {
+    const int tid = threadIdx.x, psplit = a.psplit, Rprod = a.Rprod, Rf = a.Rf;
+    if (psplit > 1) {
+#pragma unroll
+      for (int q = 0; q < SPT; ++q)
+        if (aoff[q] >= 0) comb[q * NT + tid] = acc[q];
+      __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < SPT; ++q) {
+      if (aoff[q] >= 0 && psub == 0) {
+        const int s = q * NT + tid;
+        double v = acc[q];
+        for (int t = 1; t < psplit; ++t) v += comb[s + t];
+        const int b = s / psplit;
+        const int jl = b / Rprod, sl = b - jl * Rprod;
+        int rc = sl / Rf;
+        long long col = (long long)(sl - rc * Rf) * a.ustf;
+#pragma unroll
+        for (int c = NC - 1; c >= 0; --c) {
+          const int r = rc % a.crank[c];
+          rc /= a.crank[c];
+          col += (long long)r * a.ustc[c];
+        }
+        a.Upart[((long long)sp * a.Ik + j0 + jl) * Rprod + col] = v;
+      }
+    }
+  }
+};
+
+__device__ __forceinline__ void block_norms(double dx2, double x2, double f2, double* red, double* out) {
+  const int tid = threadIdx.x;
+  const double v0 = wave_sum(dx2), v1 = wave_sum(x2), v2 = wave_sum(f2);
+  const int w = tid >> 6;
+  if ((tid & 63) == 0) {
+    red[w * 3 + 0] = v0;
+    red[w * 3 + 1] = v1;
+    red[w * 3 + 2] = v2;
+  }
+  __syncthreads();
+  if (tid < 3) {
+    double sum = 0.0;
+    for (int q = 0; q < NT / 64; ++q) sum += red[q * 3 + tid];
+    out[tid] = sum;
+  }
+}
+
+// rows variant (fibre mode contiguous) ---------------------------------------
+template <typename TX, typename TC, int NC, bool UPD, bool CON, int SPT>
+__global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const FLayout Ly = flayout((int)sizeof(TC), a);
+  long long* pbase = (long long*)(smem + Ly.pbase);
+  int* pidx = (int*)(smem + Ly.pidx);
+  double* acoef = (double*)(smem + Ly.acoef);
+  TC* sccl = (TC*)(smem + Ly.scc);
+  TC* scf = (TC*)(smem + Ly.scf);
+  TC* t0 = (TC*)(smem + Ly.t0);
+  TC* w0f = (TC*)(smem + Ly.w0f);
+  TC* gf = (TC*)(smem + Ly.gf);
+  TC* Tl = (TC*)(smem + Ly.T);
+  double* red = (double*)(smem + Ly.red);
+
+  const int tid = threadIdx.x, bid = blockIdx.x;
+  const int jt = bid % a.JT, sp = bid / a.JT;
+  const int j0 = jt * a.jn, jcnt = min(a.jn, a.Ik - j0);
+  const long long p_begin = (long long)sp * a.PPW, p_end = min(a.nplanes, p_begin + a.PPW);
+  const TC* __restrict__ Wc = (const TC*)a.Wc;
+  TX* __restrict__ X = (TX*)a.X;
+  const int If = a.If, Rf = a.Rf, jn = a.jn;
+
+  Slots<SPT> sl;
+  if (CON) {
+    sl.init(jcnt, a.Rprod, Rf, a.psplit);
+    load_gf<TC>(a, gf);
+  }
+  if (UPD)
+    for_batched<4>(
+        jcnt * If,
+        [&](int e) {
+          const int jl = e / If, ff = e - jl * If;
+          return Wc[eaddr(a.e0f, j0 + jl, ff)];
+        },
+        [&](int e, TC v) { w0f[e] = v; });
+  double dx2 = 0.0, x2 = 0.0, f2 = 0.0;
+  const TC rx = (TC)a.rho_x, inv1 = (TC)1 / ((TC)1 + rx);
+  const int fch = a.fch, rpp = NT / fch, chunk = (If + fch - 1) / fch, ch = tid & (fch - 1);
+
+  for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
+    const int np = (int)min((long long)a.PB, p_end - pb0);
+    plane_setup<TC, NC>(a, pb0, np, jcnt, j0, pbase, pidx, sccl, scf, acoef, t0, CON, UPD);
+    const int rows = np * jcnt;
+    const int passes = (rows + rpp - 1) / rpp;
+    for (int ps = 0; ps < passes; ++ps) {
+      const int row = ps * rpp + tid / fch;
+      TC t[MAXR];
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) t[r] = (TC)0;
+      const bool rok = row < rows;
+      const int rowc = rok ? row : rows - 1;
+      const int pl = a.plfast ? rowc % np : rowc / jcnt;
+      const int jl = a.plfast ? rowc / np : rowc % jcnt;
+      const long long base = pbase[pl] + (long long)(j0 + jl) * a.stride_k;
+      const TC* sr = scf + pl * If;
+      const TC* wr = w0f + jl * If;
+      const TC tt = UPD ? t0[pl * jn + jl] : (TC)0;
+      const int lo = ch * chunk, hi = rok ? min(If, lo + chunk) : lo;
+      for (int f0 = lo; f0 < hi; f0 += 4) {
+        TX xv[4];
+        uint32_t mw[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const long long L = base + min(f0 + u, hi - 1);
+          xv[u] = X[L];
+          if (UPD) mw[u] = a.maskbits[L >> 5];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ff = min(f0 + u, hi - 1);
+          const bool live = f0 + u < hi;
+          TC x = (TC)xv[u];
+          const TC sk = sr[ff];
+          if (UPD) {
+            const long long L = base + ff;
+            const TC xh = sk * tt * wr[ff];
+            const bool obs = (mw[u] >> (L & 31)) & 1u;
+            const TC xn = obs ? x : (TC)(TX)((xh + rx * x) * inv1);   // as stored
+            if (live && !obs) X[L] = (TX)xn;
+            const double lv = live ? 1.0 : 0.0;
+            const double d = (double)xn - (double)x;
+            dx2 += lv * d * d;
+            x2 += lv * (double)x * (double)x;
+            const double rr = (double)xn - (double)xh;
+            f2 += lv * rr * rr;
+            x = xn;
+          }
+          if (CON) {
+            const TC y = live ? x * sk : (TC)0;
+            const TC* g = gf + ff * MAXR;
+#pragma unroll
+            for (int r = 0; r < MAXR; ++r) t[r] += y * g[r];
+          }
+        }
+      }
+      if (CON) {
+        for (int o = 1; o < fch; o <<= 1) {
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r) t[r] += __shfl_xor(t[r], o, 64);
+        }
+        if (rok && ch == 0) {
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r)
+            if (r < Rf) Tl[(pl * jn + jl) * Rf + r] = t[r];
+        }
+      }
+    }
+    __syncthreads();
+    if (CON) sl.accumulate(acoef, Tl, np, jn, a.Rc, Rf, a.psplit);
+    __syncthreads();
+  }
+  if (CON) sl.template write<NC>(a, (double*)(smem + Ly.T), sp, j0);
+  if (UPD) block_norms(dx2, x2, f2, red, a.normpart + (long long)bid * 3);
+}
+
+// columns variant (mode k contiguous) ----------------------------------------
+template <typename TX, typename TC, int NC, int SPT>
+__global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  const FLayout Ly = flayout((int)sizeof(TC), a);
+  long long* pbase = (long long*)(smem + Ly.pbase);
+  int* pidx = (int*)(smem + Ly.pidx);
+  double* acoef = (double*)(smem + Ly.acoef);
+  TC* sccl = (TC*)(smem + Ly.scc);
+  TC* scf = (TC*)(smem + Ly.scf);
+  TC* t0 = (TC*)(smem + Ly.t0);
+  TC* gf = (TC*)(smem + Ly.gf);
+  TC* Tl = (TC*)(smem + Ly.T);
+  TC* tpart = (TC*)(smem + Ly.tpart);
+
+  const int tid = threadIdx.x, bid = blockIdx.x;
+  const int jt = bid % a.JT, spf = bid / a.JT;          // partial index = plane split * FS + fibre split
+  const int sp = spf / a.FS, fs = spf - sp * a.FS;
+  const int j0 = jt * a.jn, jcnt = min(a.jn, a.Ik - j0);
+  const long long p_begin = (long long)sp * a.PPW, p_end = min(a.nplanes, p_begin + a.PPW);
+  const TX* __restrict__ X = (const TX*)a.X;
+  const int If = a.If, Rf = a.Rf, jn = a.jn;
+  const int fcs = (If + a.FS - 1) / a.FS, flo = fs * fcs, fhi = min(If, flo + fcs);
+  const long long sf = a.stride_f;
+
+  Slots<SPT> sl;
+  sl.init(jcnt, a.Rprod, Rf, a.psplit);
+  load_gf<TC>(a, gf);
+
+  for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
+    const int np = (int)min((long long)a.PB, p_end - pb0);
+    plane_setup<TC, NC>(a, pb0, np, jcnt, j0, pbase, pidx, sccl, scf, acoef, t0, true, false);
+    const int NI = np * jcnt;                     // (plane, j) columns of this batch
+    const int fg = NI >= NT ? 1 : NT / NI;        // fibre groups within the workgroup
+    const int fchunk = (fhi - flo + fg - 1) / fg;
+    const int npass = fg > 1 ? 1 : (NI + NT - 1) / NT;
+    for (int ps = 0; ps < npass; ++ps) {
+      const int g = fg > 1 ? tid / NI : 0;
+      const int it = fg > 1 ? tid - g * NI : ps * NT + tid;
+      const bool ok = g < fg && it < NI;
+      const int itc = ok ? it : NI - 1;
+      TC t[MAXR];
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) t[r] = (TC)0;
+      const int pl = itc / jcnt, jl = itc - pl * jcnt;
+      const TC* sr = scf + pl * If;
+      const long long base = pbase[pl] + j0 + jl;
+      const int lo = flo + (ok ? g : 0) * fchunk, hi = ok ? min(fhi, lo + fchunk) : lo;
+      for (int f0 = lo; f0 < hi; f0 += 4) {
+        TX xv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) xv[u] = X[base + (long long)min(f0 + u, hi - 1) * sf];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ff = min(f0 + u, hi - 1);
+          const TC y = (f0 + u < hi) ? (TC)xv[u] * sr[ff] : (TC)0;
+          const TC* gg = gf + ff * MAXR;
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r) t[r] += y * gg[r];
+        }
+      }
+      if (fg > 1) {
+        if (ok) {
+#pragma unroll
+          for (int r = 0; r < MAXR; ++r)
+            if (r < Rf) tpart[(g * NI + it) * Rf + r] = t[r];
+        }
+        __syncthreads();
+        for (int e = tid; e < NI * Rf; e += NT) {
+          TC v = (TC)0;
+          for (int q = 0; q < fg; ++q) v += tpart[q * NI * Rf + e];
+          const int i2 = e / Rf, r = e - i2 * Rf;
+          const int p2 = i2 / jcnt, j2 = i2 - p2 * jcnt;
+          Tl[(p2 * jn + j2) * Rf + r] = v;
+        }
+      } else if (ok) {
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r)
+          if (r < Rf) Tl[(pl * jn + jl) * Rf + r] = t[r];
+      }
+    }
+    __syncthreads();
+    sl.accumulate(acoef, Tl, np, jn, a.Rc, Rf, a.psplit);
+    __syncthreads();
+  }
+  sl.template write<NC>(a, (double*)(smem + Ly.T), spf, j0);
+}
+
+// Per-launch timing (events set by set_kernel_events; see ifctn_kernels.hip)
+extern thread_local hipEvent_t tl_ev_start, tl_ev_stop;
+extern thread_local bool tl_ev_used;
+
+#define IFCTN_GO(kern, grid, blk, smem, s, ...)                                                   \
+  do {                                                                                            \
+    if (tl_ev_start) {                                                                            \
+      hipExtLaunchKernelGGL(kern, grid, blk, smem, s, tl_ev_start, tl_ev_stop, 0u, __VA_ARGS__);  \
+      tl_ev_used = true;                                                                          \
+    } else {                                                                                      \
+      hipLaunchKernelGGL(kern, grid, blk, smem, s, __VA_ARGS__);                                  \
+    }                                                                                             \
+  } while (0)
+template <typename TX, typename TC>
+static hipError_t contract_dispatch(bool upd, bool con, int spt, const ContractArgs& a, size_t smem,
+                                    hipStream_t s) {
+  const dim3 grid((unsigned)(a.JT * a.S)), blk(NT);
+#define IFCTN_CASE(U, C, P)                                                      \
+  if (upd == U && con == C && spt == P) {                                        \
+    IFCTN_GO((k_contract<TX, TC, U, C, P>), grid, blk, smem, s, a);             \
+    return hipGetLastError();                                                    \
+  }
+  IFCTN_CASE(true, false, 1)
+  IFCTN_CASE(false, true, 1) IFCTN_CASE(false, true, 2) IFCTN_CASE(false, true, 4)
+  IFCTN_CASE(false, true, 8) IFCTN_CASE(false, true, 16) IFCTN_CASE(false, true, 32)
+  IFCTN_CASE(true, true, 1) IFCTN_CASE(true, true, 2) IFCTN_CASE(true, true, 4)
+  IFCTN_CASE(true, true, 8) IFCTN_CASE(true, true, 16) IFCTN_CASE(true, true, 32)
+#undef IFCTN_CASE
+  return hipErrorInvalidValue;
+}
+
+template <typename TX, typename TC, int NC>
+static hipError_t fast_dispatch_nc(bool upd, bool con, int spt, const ContractArgs& a, size_t smem, hipStream_t s) {
+  const dim3 grid((unsigned)(a.JT * a.S * a.FS)), blk(NT);
+  if (a.kind == 1) {
+#define IFCTN_ROWS(U, C, P)                                                              \
+  if (upd == U && con == C && spt == P) {                                                \
+    IFCTN_GO((k_contract_rows<TX, TC, NC, U, C, P>), grid, blk, smem, s, a);             \
+    return hipGetLastError();                                                            \
+  }
+    IFCTN_ROWS(true, false, 1)
+    IFCTN_ROWS(false, true, 1) IFCTN_ROWS(false, true, 2) IFCTN_ROWS(false, true, 4) IFCTN_ROWS(false, true, 8)
+    IFCTN_ROWS(true, true, 1) IFCTN_ROWS(true, true, 2) IFCTN_ROWS(true, true, 4) IFCTN_ROWS(true, true, 8)
+#undef IFCTN_ROWS
+  } else if (a.kind == 2 && con && !upd) {
+#define IFCTN_COLS(P)                                                              \
+  if (spt == P) {                                                                  \
+    IFCTN_GO((k_contract_cols<TX, TC, NC, P>), grid, blk, smem, s, a);             \
+    return hipGetLastError();                                                      \
+  }
+    IFCTN_COLS(1) IFCTN_COLS(2) IFCTN_COLS(4) IFCTN_COLS(8)
+#undef IFCTN_COLS
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename TX, typename TC>
+static hipError_t fast_dispatch(bool upd, bool con, int spt, const ContractArgs& a, size_t smem, hipStream_t s) {
+  switch (a.nc) {
+    case 0: return fast_dispatch_nc<TX, TC, 0>(upd, con, spt, a, smem, s);
+    case 1: return fast_dispatch_nc<TX, TC, 1>(upd, con, spt, a, smem, s);
+    case 2: return fast_dispatch_nc<TX, TC, 2>(upd, con, spt, a, smem, s);
+    default: return fast_dispatch_nc<TX, TC, 3>(upd, con, spt, a, smem, s);
+  }
+}
+
+}  // namespace ifctn

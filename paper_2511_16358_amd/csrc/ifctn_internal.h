@@ -14,6 +14,25 @@ constexpr int MAXC = MAXN - 2;       // modes other than k and the fibre mode
 constexpr int MAXP = MAXR * (MAXR + 1) / 2;  // distinct entries of an R x R Gram matrix
 constexpr int NT = 256;              // threads per workgroup (4 wavefronts of 64)
 
+// bfloat16 storage of X: the upper half of an IEEE binary32.  Narrowing rounds
+// to nearest, ties to even (add 0x7fff plus the lowest kept bit, truncate);
+// NaN stays NaN.  Widening is exact.
+struct bf16x {
+  uint16_t v;
+  bf16x() = default;
+  __device__ explicit bf16x(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u)
+      v = (uint16_t)((u >> 16) | 0x40u);
+    else
+      v = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+  __device__ explicit operator float() const { return __uint_as_float((uint32_t)v << 16); }
+};
+
+// kernel data types: X storage / streaming arithmetic
+enum KType { KT_F32 = 0, KT_F64 = 1, KT_BF16 = 2 };  // KT_BF16: bf16 X, float arithmetic
+
 // Oriented reference to an edge matrix: W(i_first, i_second) lives at
 // base[off + i_first * s1 + i_second * s2].  Edge {a,b}, a < b, is stored
 // row-major I_a x I_b, so the reversed orientation just swaps the strides.
@@ -144,8 +163,16 @@ enum KernelClass { KC_CONTRACT = 0, KC_SOLVE = 1, KC_UPDATE = 2, KC_GRAM = 3, KC
 // dtype: 0 = float32 streaming data, 1 = float64
 hipError_t launch_init_x(int dtype, const void* O, const uint8_t* mask, void* X, uint32_t* maskbits,
                          int* bad_flag, long long nX, hipStream_t s);
+// X_bf16 = bf16(X32) / out = observed ? X32 : float(X_bf16) (exact widening)
+hipError_t launch_narrow(const float* X32, bf16x* Xb, long long nX, hipStream_t s);
+hipError_t launch_widen(const bf16x* Xb, const uint32_t* maskbits, const float* X32, float* out, long long nX,
+                        hipStream_t s);
 hipError_t launch_edge(int dtype, const double* Gab, const double* Gba, int R, int Ia, int Ib,
                        double* W64, void* Wc, hipStream_t s);
+// one per X storage type (ifctn_contract_*.hip)
+hipError_t launch_contract_f32(bool upd, bool con, int spt, const ContractArgs& a, size_t smem, hipStream_t s);
+hipError_t launch_contract_f64(bool upd, bool con, int spt, const ContractArgs& a, size_t smem, hipStream_t s);
+hipError_t launch_contract_bf16(bool upd, bool con, int spt, const ContractArgs& a, size_t smem, hipStream_t s);
 hipError_t launch_contract(int dtype, bool upd, bool con, int spt, const ContractArgs& a,
                            size_t smem, hipStream_t s);
 size_t contract_smem_bytes(int dtype, const ContractArgs& a);

@@ -32,6 +32,7 @@ EXPORTED = [
     "ifctn_num_factor_entries", "ifctn_workspace_bytes", "ifctn_init", "ifctn_sweep",
     "ifctn_reconstruct", "ifctn_get_factors", "ifctn_destroy", "ifctn_complete",
     "ifctn_assemble", "ifctn_timing_enable", "ifctn_timing_query", "ifctn_last_error",
+    "ifctn_promote",
 ]
 
 
@@ -94,6 +95,7 @@ def lib():
         "ifctn_timing_enable": (st, [vp, i32]),
         "ifctn_timing_query": (st, [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]),
         "ifctn_last_error": (ctypes.c_char_p, []),
+        "ifctn_promote": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -108,7 +110,7 @@ def _check(status):
         raise IfctnError(status, lib().ifctn_last_error().decode())
 
 
-def make_params(dims, ranks, rho=0.1, rho_x=0.0, precision=IFCTN_FP32) -> IfctnParams:
+def make_params(dims, ranks, rho=0.1, rho_x=0.0, precision=IFCTN_FP32, refine_sweeps=0) -> IfctnParams:
     p = IfctnParams()
     p.order = len(dims)
     for m, d in enumerate(dims):
@@ -116,7 +118,7 @@ def make_params(dims, ranks, rho=0.1, rho_x=0.0, precision=IFCTN_FP32) -> IfctnP
     for a in range(len(dims)):
         for b in range(len(dims)):
             p.ranks[a][b] = int(ranks[a][b]) if a != b else 0
-    p.rho, p.rho_x, p.precision, p.refine_sweeps = float(rho), float(rho_x), int(precision), 0
+    p.rho, p.rho_x, p.precision, p.refine_sweeps = float(rho), float(rho_x), int(precision), int(refine_sweeps)
     return p
 
 
@@ -181,6 +183,10 @@ class Job:
         _check(lib().ifctn_get_factors(self.handle, _dptr(buf)))
         return workloads.unpack(buf, self.dims, self.ranks)
 
+    def promote(self):
+        """End the bfloat16 phase of a BF16_REFINE job (later sweeps stream float32)."""
+        _check(lib().ifctn_promote(self.handle))
+
     def timing(self, enable: bool):
         _check(lib().ifctn_timing_enable(self.handle, 1 if enable else 0))
 
@@ -201,10 +207,10 @@ class Job:
             pass
 
 
-def complete(O, mask, G0, dims, ranks, t_max, eps=0.0, rho=0.1, precision=IFCTN_FP32):
+def complete(O, mask, G0, dims, ranks, t_max, eps=0.0, rho=0.1, precision=IFCTN_FP32, refine_sweeps=0):
     """Algorithm 1 end to end through ifctn_complete; returns (X, stats)."""
     dims = tuple(int(d) for d in dims)
-    params = make_params(dims, ranks, rho, 0.0, precision)
+    params = make_params(dims, ranks, rho, 0.0, precision, refine_sweeps)
     dt = _dtype(precision)
     Ot = torch.as_tensor(np.asarray(O)).to(device="cuda", dtype=dt).contiguous()
     Mt = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to("cuda").contiguous()
