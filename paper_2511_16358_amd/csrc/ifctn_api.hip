@@ -435,6 +435,10 @@ struct ifctn_job {
   int nnorm = 0, ndg = 0;
   bool pending = false;
   int sweeps_done = 0;
+  // device-side stop test (Algorithm 1) after every X step: flag[1] = stop,
+  // flag[2] = sweeps completed before the stop
+  bool dev_stop = false;
+  double stop_eps = 0.0;
   bool timing = false;
   std::vector<hipEvent_t> ev[KC_COUNT];
   size_t evn[KC_COUNT] = {0, 0, 0, 0};
@@ -619,6 +623,10 @@ hipError_t run_sweep(ifctn_job* J) {
     ContractCall cc{k, k == 0 && J->pending, true};
     e = timed(J, KC_CONTRACT, do_contract, &cc);
     if (e != hipSuccess) return e;
+    if (cc.upd && J->dev_stop) {
+      e = launch_stop_test(J->normpart, J->nnorm, J->stop_eps, J->flag + 1, J->stream);
+      if (e != hipSuccess) return e;
+    }
     e = timed(J, KC_SOLVE, do_solve, &J->splan[k]);
     if (e != hipSuccess) return e;
   }
@@ -632,8 +640,17 @@ hipError_t flush_update(ifctn_job* J) {
   ContractCall cc{0, true, false};
   hipError_t e = timed(J, KC_UPDATE, do_contract, &cc);
   J->pending = false;
+  if (e == hipSuccess && J->dev_stop) e = launch_stop_test(J->normpart, J->nnorm, J->stop_eps, J->flag + 1, J->stream);
   return e;
 }
+
+// Algorithm 1's loop for an initialised job.  With eps > 0 the stop test runs
+// on the device after every X step (k_stop_test); once it is met every later
+// launch of the job is a no-op, so the host issues sweeps in chunks and reads
+// the flag once per chunk instead of once per sweep.
+constexpr int kStopChunk = 8;
+
+ifctn_status run_complete(ifctn_job* J, int t_max, double eps, void* X_out_dev, ifctn_stats* out);
 
 // End the bfloat16 phase: the float32 master takes the widened bf16 values off
 // Omega (it holds O on Omega), and every later pass streams float32.
@@ -646,6 +663,60 @@ hipError_t promote(ifctn_job* J) {
   J->bf16_phase = false;
   for (int k = 0; k < J->g.N; ++k) J->cplan[k].a.X = J->X;
   return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" ifctn_status ifctn_sweep(ifctn_job* J, int32_t nsweeps, ifctn_stats* stats);
+extern "C" ifctn_status ifctn_reconstruct(ifctn_job* J, void* out_dev, int32_t which);
+
+namespace {
+
+ifctn_status run_complete(ifctn_job* J, int t_max, double eps, void* X_out_dev, ifctn_stats* out) {
+  ifctn_stats s;
+  std::memset(&s, 0, sizeof(s));
+  // BF16_REFINE: the last `refine` sweeps stream float32 (after promotion)
+  const int refine = std::min(J->g.refine, t_max);
+  const int t_main = t_max - refine;
+  int state[2] = {0, 0};
+  int done_main = t_main;
+  if (eps > 0.0 && t_main > 0) {
+    J->dev_stop = true;
+    J->stop_eps = eps;
+    HIPTRY(hipMemsetAsync(J->flag + 1, 0, 2 * sizeof(int), J->stream));
+    for (int t = 0; t < t_main; t += kStopChunk) {
+      const int n = std::min(kStopChunk, t_main - t);
+      for (int q = 0; q < n; ++q) HIPTRY(run_sweep(J));
+      if (t + n >= t_main) HIPTRY(flush_update(J));   // X step (and stop test) of the last sweep
+      HIPTRY(hipMemcpyAsync(state, J->flag + 1, sizeof(state), hipMemcpyDeviceToHost, J->stream));
+      HIPTRY(hipStreamSynchronize(J->stream));
+      if (state[0]) break;
+    }
+    if (state[0]) HIPTRY(flush_update(J));              // a no-op on the device: the job has stopped
+    done_main = state[1];
+    J->dev_stop = false;
+  } else if (t_main > 0) {
+    for (int q = 0; q < t_main; ++q) HIPTRY(run_sweep(J));
+    HIPTRY(flush_update(J));
+  }
+  ifctn_status st = IFCTN_OK;
+  if (J->g.bf16) {
+    HIPTRY(promote(J));
+    if (refine > 0) {
+      HIPTRY(hipMemsetAsync(J->flag + 1, 0, 2 * sizeof(int), J->stream));   // the refinement always runs
+      for (int q = 0; q < refine; ++q) HIPTRY(run_sweep(J));
+      HIPTRY(flush_update(J));
+    }
+  }
+  st = ifctn_sweep(J, 0, &s);                            // statistics of the last sweep run
+  if (st != IFCTN_OK) return st;
+  s.sweeps_done = done_main + refine;
+  s.converged = state[0];
+  st = ifctn_reconstruct(J, X_out_dev, 1);
+  if (st != IFCTN_OK) return st;
+  HIPTRY(hipStreamSynchronize(J->stream));
+  if (out) *out = s;
+  return IFCTN_OK;
 }
 
 }  // namespace
@@ -742,9 +813,12 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
     J->qplan[k].G = J->G;
     J->qplan[k].Q = J->Q;
     J->qplan[k].dit = dq + (size_t)k * (MAXN - 1);
+    a.stop = J->flag + 1;
+    J->qplan[k].stop = J->flag + 1;
   }
   J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
   build_solve_plans(J);
+  for (int k = 0; k < g.N; ++k) J->splan[k].stop = J->flag + 1;
   for (int k = 0; k < g.N; ++k) {
     if (solve_smem_bytes(J->splan[k]) > kMaxLds) {
       (void)hipFree(J->arena);
@@ -860,36 +934,7 @@ ifctn_status ifctn_complete(const ifctn_params* params, const void* O_dev, const
   ifctn_job* J = nullptr;
   ifctn_status st = ifctn_init(params, O_dev, mask_dev, G0_host, stream, &J);
   if (st != IFCTN_OK) return st;
-  ifctn_stats s;
-  std::memset(&s, 0, sizeof(s));
-  // BF16_REFINE: the last `refine` sweeps stream float32 (after promotion)
-  const int refine = std::min(J->g.refine, t_max);
-  const int t_main = t_max - refine;
-  int converged = 0;
-  if (eps == 0.0) {
-    if (t_main > 0) st = ifctn_sweep(J, t_main, &s);
-  } else {
-    for (int t = 0; t < t_main; ++t) {
-      st = ifctn_sweep(J, 1, &s);
-      if (st != IFCTN_OK) break;
-      if (s.rel_change < eps) {
-        converged = 1;
-        break;
-      }
-    }
-  }
-  if (st == IFCTN_OK && J->g.bf16) {
-    hipError_t e = promote(J);
-    if (e != hipSuccess) st = fail(IFCTN_E_HIP, "promote: %s", hipGetErrorString(e));
-    if (st == IFCTN_OK && refine > 0) st = ifctn_sweep(J, refine, &s);
-  }
-  s.converged = converged;
-  if (st == IFCTN_OK) st = ifctn_reconstruct(J, X_out_dev, 1);
-  if (st == IFCTN_OK) {
-    hipError_t e = hipStreamSynchronize(J->stream);
-    if (e != hipSuccess) st = fail(IFCTN_E_HIP, "hipStreamSynchronize: %s", hipGetErrorString(e));
-  }
-  if (st == IFCTN_OK && stats) *stats = s;
+  st = run_complete(J, t_max, eps, X_out_dev, stats);
   ifctn_destroy(J);
   return st;
 }

@@ -91,6 +91,7 @@ constexpr int UNR = 8;   // X elements in flight per thread in the streaming sta
 
 template <typename TX, typename TC, bool UPD, bool CON, int SPT>
 __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
+  if (a.stop && *a.stop) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const CLayout Ly = clayout((int)sizeof(TC), a);
   long long* pbase = (long long*)(smem + Ly.pbase);
@@ -601,6 +602,7 @@ __device__ __forceinline__ void block_norms(double dx2, double x2, double f2, do
 // rows variant (fibre mode contiguous) ---------------------------------------
 template <typename TX, typename TC, int NC, bool UPD, bool CON, int SPT>
 __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
+  if (a.stop && *a.stop) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const FLayout Ly = flayout((int)sizeof(TC), a);
   long long* pbase = (long long*)(smem + Ly.pbase);
@@ -718,6 +720,7 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
 // columns variant (mode k contiguous) ----------------------------------------
 template <typename TX, typename TC, int NC, int SPT>
 __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
+  if (a.stop && *a.stop) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const FLayout Ly = flayout((int)sizeof(TC), a);
   long long* pbase = (long long*)(smem + Ly.pbase);

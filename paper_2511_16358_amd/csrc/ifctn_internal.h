@@ -60,6 +60,7 @@ struct QArgs {
   const double* W64;
   const double* G;
   double* Q;
+  const int* stop;            // device stop flag: nonzero = the job has met its stop test
 };
 
 // Mode-k contraction U_k(j, r_{-k}) = sum_{i_{-k}} X(i) S_k(i_{-k}) prod_{m != k}
@@ -107,6 +108,7 @@ struct ContractArgs {
   const double* G;       // packed float64 factors
   double* Upart;         // [S][I_k][Rprod] split partial sums
   double* normpart;      // [blocks][3]: ||dX||^2, ||X||^2, ||X_new - Xhat||^2
+  const int* stop;       // device stop flag (every launch of a stopped job is a no-op)
 };
 
 // Factor block k (all G_{k,i}, i != k, in ascending i), one workgroup per
@@ -143,6 +145,7 @@ struct SolveArgs {
   void* Wc;
   double* G;
   double* dgpart;                // [nsub][Ik]
+  const int* stop;               // device stop flag
 };
 
 struct ReconArgs {
@@ -183,6 +186,11 @@ bool kernel_events_used();
 hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s);
 size_t solve_smem_bytes(const SolveArgs& a);
 hipError_t launch_reconstruct(int dtype, const ReconArgs& a, hipStream_t s);
+// Stop test of Algorithm 1 on the device, after an X step: reduces the
+// partial norms like launch_finalize and, unless state[0] (stop flag) is
+// already set, counts the sweep in state[1] and sets state[0] when
+// ||dX|| / ||X|| < eps.
+hipError_t launch_stop_test(const double* normpart, int nnorm, double eps, int* state, hipStream_t s);
 hipError_t launch_finalize(const double* normpart, int nnorm, const double* dgpart, int ndg,
                            double* out5, hipStream_t s);
 

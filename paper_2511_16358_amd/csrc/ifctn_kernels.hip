@@ -160,6 +160,7 @@ __device__ __forceinline__ void gram_work(const double* __restrict__ W64, const 
 }
 
 __global__ __launch_bounds__(NT) void k_gram_q(QArgs a) {
+  if (a.stop && *a.stop) return;
   // constant indices into the argument block; the per-i records come from
   // device memory (a runtime index into the argument block would force a
   // copy of it into scratch memory)
@@ -260,6 +261,7 @@ __host__ __device__ inline size_t solve_layout(const SolveArgs& a, size_t* o_u, 
 
 template <typename TC>
 __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
+  if (a.stop && *a.stop) return;
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   size_t ou, orw, ow, op, og, om;
   solve_layout(a, &ou, &orw, &ow, &op, &og, &om);
@@ -481,10 +483,11 @@ __global__ __launch_bounds__(NT) void k_reconstruct(ReconArgs a) {
 // K7: fixed-order finalisation of the sweep statistics
 // out5 = {||dX||^2, ||X^s||^2, ||X^{s+1} - Xhat||^2, sum ||dG||^2, 0}
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_finalize(const double* __restrict__ normpart, int nnorm,
-                                                 const double* __restrict__ dgpart, int ndg,
-                                                 double* __restrict__ out5) {
-  __shared__ double s[4][NT];
+// fixed-order sums of the per-block partials (the same order for the stop
+// test and the statistics, so both see the same numbers)
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ normpart, int nnorm,
+                                                const double* __restrict__ dgpart, int ndg, double (*s)[NT],
+                                                double* out4) {
   const int tid = threadIdx.x;
   double v[4] = {0, 0, 0, 0};
   for (int b = tid; b < nnorm; b += NT)
@@ -497,8 +500,34 @@ __global__ __launch_bounds__(NT) void k_finalize(const double* __restrict__ norm
       for (int c = 0; c < 4; ++c) s[c][tid] += s[c][tid + w];
     __syncthreads();
   }
-  if (tid < 4) out5[tid] = s[tid][0];
+  for (int c = 0; c < 4; ++c) out4[c] = s[c][0];
+}
+
+__global__ __launch_bounds__(NT) void k_finalize(const double* __restrict__ normpart, int nnorm,
+                                                 const double* __restrict__ dgpart, int ndg,
+                                                 double* __restrict__ out5) {
+  __shared__ double s[4][NT];
+  double r[4];
+  reduce_partials(normpart, nnorm, dgpart, ndg, s, r);
+  const int tid = threadIdx.x;
+  if (tid < 4) out5[tid] = r[tid];
   if (tid == 4) out5[4] = 0.0;
+}
+
+// Algorithm 1's stop test after an X step: state[0] = stop flag, state[1] =
+// sweeps completed while the flag was clear.
+__global__ __launch_bounds__(NT) void k_stop_test(const double* __restrict__ normpart, int nnorm, double eps,
+                                                  int* __restrict__ state) {
+  __shared__ double s[4][NT];
+  if (state[0]) return;                          // uniform: every lane reads the same flag
+  double r[4];
+  reduce_partials(normpart, nnorm, nullptr, 0, s, r);
+  if (threadIdx.x == 0) {
+    const double dx2 = r[0], x2 = r[1];
+    const double rel = x2 > 0.0 ? sqrt(dx2 / x2) : (dx2 == 0.0 ? 0.0 : INFINITY);
+    state[1] += 1;
+    if (rel < eps) state[0] = 1;
+  }
 }
 
 // --------------------------------------------------------------------------
@@ -592,6 +621,11 @@ hipError_t launch_reconstruct(int dtype, const ReconArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_reconstruct<float>, dim3(nblk(a.nX)), dim3(NT), 0, s, a);
   else
     hipLaunchKernelGGL(k_reconstruct<double>, dim3(nblk(a.nX)), dim3(NT), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_stop_test(const double* normpart, int nnorm, double eps, int* state, hipStream_t s) {
+  hipLaunchKernelGGL(k_stop_test, dim3(1), dim3(NT), 0, s, normpart, nnorm, eps, state);
   return hipGetLastError();
 }
 

@@ -176,6 +176,70 @@ def test_complete_stop_rule_matches_oracle():
     assert relerr(X.cpu().numpy(), Xo) < 1e-10
 
 
+@pytest.mark.parametrize("target", [0, 6, 7, 8, 9, 13])
+def test_device_stop_flag_at_chunk_boundaries(target):
+    """The stop test runs on the device after every X step and the host reads
+    the flag once per chunk of sweeps: the stop sweep must be the oracle's
+    wherever it falls relative to the chunks."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem((9, 8, 10), W.uniform_ranks(3, 2), seed=33)
+    O64 = p.O.astype(np.float64)
+    _, _, hist = oracle.pam(O64, p.mask, p.G0, p.dims, rho=0.1, t_max=16, eps=0.0)
+    rels = [h["rel_change"] for h in hist]
+    lo = min(rels[:target]) if target else np.inf
+    if not rels[target] < lo:
+        pytest.skip("relative change not decreasing at this sweep")
+    eps = 0.5 * (rels[target] + min(lo, 2 * rels[target]))
+    stop = next(s for s in range(16) if rels[s] < eps)
+    assert stop == target
+    X, st = ifctn.complete(O64, p.mask, p.G0, p.dims, p.ranks, t_max=16, eps=eps, precision=ifctn.IFCTN_FP64)
+    assert st["sweeps_done"] == stop + 1 and st["converged"] == 1
+    Xo, _, ho = oracle.pam(O64, p.mask, p.G0, p.dims, rho=0.1, t_max=16, eps=eps)
+    assert len(ho) == stop + 1
+    assert relerr(X.cpu().numpy(), Xo) < 1e-10
+    assert abs(st["rel_change"] - ho[-1]["rel_change"]) <= 1e-9 * ho[-1]["rel_change"]
+
+
+def test_device_stop_never_met_runs_t_max():
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem((9, 8, 10), W.uniform_ranks(3, 2), seed=34)
+    O64 = p.O.astype(np.float64)
+    X, st = ifctn.complete(O64, p.mask, p.G0, p.dims, p.ranks, t_max=11, eps=1e-300, precision=ifctn.IFCTN_FP64)
+    assert st["sweeps_done"] == 11 and st["converged"] == 0
+    Xo, _, _ = oracle.pam(O64, p.mask, p.G0, p.dims, rho=0.1, t_max=11, eps=0.0)
+    assert relerr(X.cpu().numpy(), Xo) < 1e-10
+
+
+def test_paper_defaults_planted30():
+    """Algorithm 1 with the paper's defaults (t_max = 1000, eps = 1e-5,
+    rho = 0.1) on the planted 30^3 tensor: same stop sweep as the oracle."""
+    from paper_2511_16358_amd import ifctn
+    p = W.problem("planted30", 0, lambda d, r, G: oracle.reconstruct(G, d))
+    O64 = p.O.astype(np.float64)
+    Xo, _, ho = oracle.pam(O64, p.mask, p.G0, p.dims, rho=0.1, t_max=1000, eps=1e-5)
+    X, st = ifctn.complete(O64, p.mask, p.G0, p.dims, p.ranks, t_max=1000, eps=1e-5, precision=ifctn.IFCTN_FP64)
+    print(f"planted30 defaults: oracle stops after {len(ho)} sweeps, GPU after {st['sweeps_done']}")
+    assert st["sweeps_done"] == len(ho) and st["converged"] == 1
+    assert relerr(X.cpu().numpy(), Xo) < 1e-9
+    X32, st32 = ifctn.complete(p.O, p.mask, p.G0, p.dims, p.ranks, t_max=1000, eps=1e-5)
+    assert abs(st32["sweeps_done"] - len(ho)) <= 2
+    assert relerr(X32.cpu().numpy(), p.X_true) < 2 * relerr(Xo, p.X_true) + 1e-4
+
+
+def test_bf16_refine_with_stop_rule():
+    """BF16_REFINE with eps: the bfloat16 phase stops on the device test,
+    then the float32 refinement sweeps run."""
+    from paper_2511_16358_amd import ifctn
+    p = W.problem("planted30", 0, lambda d, r, G: oracle.reconstruct(G, d))
+    X, st = ifctn.complete(p.O, p.mask, p.G0, p.dims, p.ranks, t_max=1000, eps=1e-3,
+                           precision=ifctn.IFCTN_BF16_REFINE, refine_sweeps=20)
+    assert st["converged"] == 1 and st["sweeps_done"] < 1000
+    _, _, ho = oracle.pam(p.O.astype(np.float64), p.mask, p.G0, p.dims, rho=0.1, t_max=1000, eps=1e-3)
+    assert abs(st["sweeps_done"] - 20 - len(ho)) <= 3
+    m = p.mask.astype(bool)
+    assert np.array_equal(X.cpu().numpy()[m], p.O[m])
+
+
 def test_invalid_inputs_rejected():
     from paper_2511_16358_amd import ifctn
     p = W.random_problem((6, 5, 4), W.uniform_ranks(3, 2), seed=1)
