@@ -154,6 +154,73 @@ ifctn_status ifctn_timing_enable(ifctn_job* job, int32_t enable);
 ifctn_status ifctn_timing_query(ifctn_job* job, int32_t kernel_class, double* total_ms,
                                 int64_t* launches);
 
+/* ---------------------------------------------------------------------------
+ * Serving: continuous batching of completion requests on one GPU.
+ *
+ * A server owns a device pool of hbm_budget_bytes (allocated once at create)
+ * and a scheduler thread.  Submitted requests wait in a FIFO queue and are
+ * admitted when one of max_active slots is free and the pool has room for the
+ * job's workspace (ifctn_workspace_bytes); a request needing more than the
+ * whole budget is refused at submit.  Each resident job runs Algorithm 1
+ * (t_max, eps, and for BF16_REFINE the float32 refinement sweeps, as in
+ * ifctn_complete) in rounds of sweeps_per_round sweeps on one of num_streams
+ * HIP streams, with the stop test on the device; jobs admitted while others
+ * run overlap with them on the device.  A job runs the same kernels in the
+ * same order as ifctn_complete, so its result does not depend on the mix.
+ * ------------------------------------------------------------------------- */
+typedef struct ifctn_server ifctn_server;
+
+typedef struct {
+  size_t hbm_budget_bytes;  /* device pool for resident jobs, allocated at create     */
+  int32_t max_active;       /* jobs resident at once (slots), 1..1024                  */
+  int32_t num_streams;      /* HIP streams the resident jobs are spread over, 1..16    */
+  int32_t sweeps_per_round; /* sweeps issued per job between two looks at its flags, >= 1 */
+  int32_t device;           /* HIP device ordinal the server runs on                   */
+} ifctn_server_config;
+
+typedef struct {
+  ifctn_params params;
+  const void* O_dev;        /* device, as for ifctn_init; complete before submit (the server's
+                               streams do not wait for the caller's); the caller keeps it valid
+                               until the request's completion has been polled                */
+  const uint8_t* mask_dev;  /* device, same rules                                            */
+  const double* G0_host;    /* packed initial factors; copied at submit                      */
+  int32_t t_max;            /* sweeps (>= 0)                                                 */
+  double eps;               /* stop tolerance (>= 0; 0 = exactly t_max sweeps)               */
+  void* X_out_dev;          /* device, prod(dims) elements of the job's output dtype; written
+                               before the completion is reported                             */
+  uint64_t tag;             /* returned in the completion                                    */
+} ifctn_request;
+
+typedef struct {
+  uint64_t tag;
+  int32_t status;           /* ifctn_status of the request                                   */
+  ifctn_stats stats;        /* as ifctn_complete's (valid when status == IFCTN_OK)          */
+  double t_submit;          /* seconds since the server was created (steady clock)           */
+  double t_admit;
+  double t_done;
+} ifctn_completion;
+
+/* Create a server (allocates the pool and pinned host memory, starts the
+ * scheduler thread).  IFCTN_E_NOMEM when the pool does not fit. */
+ifctn_status ifctn_server_create(const ifctn_server_config* config, ifctn_server** out);
+
+/* Queue a request.  Invalid params or pointers: IFCTN_E_INVAL; a workspace
+ * larger than the whole budget: IFCTN_E_NOMEM (nothing is queued then). */
+ifctn_status ifctn_server_submit(ifctn_server* server, const ifctn_request* request);
+
+/* Move up to max finished requests into out (completion order); *n = count.
+ * wait_ms > 0 waits up to that long for the first one. */
+ifctn_status ifctn_server_poll(ifctn_server* server, ifctn_completion* out, int32_t max, int32_t* n,
+                               int32_t wait_ms);
+
+/* Requests still queued (not admitted) and finished ones not yet polled. */
+ifctn_status ifctn_server_queued(ifctn_server* server, int32_t* queued, int32_t* completed_unpolled);
+
+/* Stop admitting, drop queued requests, wait for resident jobs to finish and
+ * release everything (NULL is accepted). */
+ifctn_status ifctn_server_destroy(ifctn_server* server);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* ifctn_last_error(void);
 

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libifctn.so")
 SOURCES = ["ifctn_api.hip", "ifctn_kernels.hip", "ifctn_contract_f32.hip", "ifctn_contract_f64.hip",
-           "ifctn_contract_bf16.hip"]
+           "ifctn_contract_bf16.hip", "ifctn_server.hip"]
 
 # Packed-FP32 VALU ops are disabled for all device code (-packed-fp32-ops).
 HIPCC_FLAGS = [
@@ -51,7 +51,7 @@ def build(verbose: bool = False) -> str:
     if failed:
         raise RuntimeError(f"hipcc failed on {failed}")
     tmp = LIB + ".tmp"
-    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [cc, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "ifctn.h"
+#include "ifctn_host.h"
 #include "ifctn_internal.h"
 
 using namespace ifctn;
@@ -415,6 +416,7 @@ struct ifctn_job {
   hipStream_t stream = nullptr;
   unsigned char* arena = nullptr;
   size_t arena_bytes = 0;
+  bool own_arena = true;      // false: the arena is a slice of a server's pool
   void* X = nullptr;          // master X (float32 / float64)
   bf16x* Xb = nullptr;        // bfloat16 X of the BF16 phase (BF16_REFINE jobs)
   bool bf16_phase = false;
@@ -752,13 +754,18 @@ ifctn_status ifctn_destroy(ifctn_job* job) {
   if (!job) return IFCTN_OK;
   for (int c = 0; c < KC_COUNT; ++c)
     for (hipEvent_t e : job->ev[c]) (void)hipEventDestroy(e);
-  if (job->arena) (void)hipFree(job->arena);
+  if (job->arena && job->own_arena) (void)hipFree(job->arena);
   delete job;
   return IFCTN_OK;
 }
 
-ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
-                        const double* G0_host, void* stream, ifctn_job** out) {
+}  // extern "C"
+
+namespace ifctn {
+
+ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
+                      const double* G0_host, hipStream_t stream, unsigned char* pool, size_t pool_bytes,
+                      bool check_now, ifctn_job** out) {
   if (!out) return fail(IFCTN_E_INVAL, "out is NULL");
   *out = nullptr;
   Geo g;
@@ -777,12 +784,21 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
       return fail(IFCTN_E_UNSUPPORTED, "no valid work plan for mode %d (%s)", k, why);
     }
   }
-  hipError_t e = hipMalloc((void**)&J->arena, s.total);
-  if (e != hipSuccess) {
-    delete J;
-    (void)hipGetLastError();
-    return fail(e == hipErrorOutOfMemory ? IFCTN_E_NOMEM : IFCTN_E_HIP, "hipMalloc(%zu): %s", s.total,
-                hipGetErrorString(e));
+  if (pool) {
+    if (pool_bytes < s.total) {
+      delete J;
+      return fail(IFCTN_E_NOMEM, "pool slice of %zu bytes < %zu needed", pool_bytes, s.total);
+    }
+    J->arena = pool;
+    J->own_arena = false;
+  } else {
+    hipError_t e = hipMalloc((void**)&J->arena, s.total);
+    if (e != hipSuccess) {
+      delete J;
+      (void)hipGetLastError();
+      return fail(e == hipErrorOutOfMemory ? IFCTN_E_NOMEM : IFCTN_E_HIP, "hipMalloc(%zu): %s", s.total,
+                  hipGetErrorString(e));
+    }
   }
   J->arena_bytes = s.total;
   unsigned char* p = J->arena;
@@ -850,17 +866,76 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
     INIT_TRY(launch_edge(g.dtype, J->G + g.goff[a][b], J->G + g.goff[b][a], g.R[a][b], g.dims[a], g.dims[b],
                          J->W64 + g.woff[e2], (unsigned char*)J->Wc + g.woff[e2] * g.esz, J->stream));
   }
-  int bad = 0;
-  INIT_TRY(hipMemcpyAsync(&bad, J->flag, sizeof(int), hipMemcpyDeviceToHost, J->stream));
-  INIT_TRY(hipStreamSynchronize(J->stream));
-#undef INIT_TRY
-  if (bad) {
-    ifctn_destroy(J);
-    return fail(IFCTN_E_INVAL, "an observed entry of O is not finite");
+  if (check_now) {
+    int bad = 0;
+    INIT_TRY(hipMemcpyAsync(&bad, J->flag, sizeof(int), hipMemcpyDeviceToHost, J->stream));
+    INIT_TRY(hipStreamSynchronize(J->stream));
+    if (bad) {
+      ifctn_destroy(J);
+      return fail(IFCTN_E_INVAL, "an observed entry of O is not finite");
+    }
   }
+#undef INIT_TRY
   *out = J;
   return IFCTN_OK;
 }
+
+size_t job_bytes(const ifctn_params* params) { return ifctn_workspace_bytes(params); }
+
+hipError_t job_sweeps(ifctn_job* J, int n) {
+  for (int q = 0; q < n; ++q) {
+    hipError_t e = run_sweep(J);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t job_x_step(ifctn_job* J) { return flush_update(J); }
+
+hipError_t job_promote(ifctn_job* J) { return promote(J); }
+
+bool job_is_bf16(const ifctn_job* J) { return J->g.bf16; }
+
+int job_refine_sweeps(const ifctn_job* J) { return J->g.refine; }
+
+void job_set_stop(ifctn_job* J, double eps) {
+  J->dev_stop = eps > 0.0;
+  J->stop_eps = eps;
+}
+
+hipError_t job_reset_flags(ifctn_job* J) { return hipMemsetAsync(J->flag + 1, 0, 2 * sizeof(int), J->stream); }
+
+const int* job_flags(const ifctn_job* J) { return J->flag; }
+
+hipError_t job_finalize(ifctn_job* J) {
+  return launch_finalize(J->normpart, J->nnorm, J->dgpart, J->ndg, J->stats5, J->stream);
+}
+
+const double* job_stats_dev(const ifctn_job* J) { return J->stats5; }
+
+void stats_from(const double* h, int sweeps_done, ifctn_stats* out) {
+  out->dx_norm2 = h[0];
+  out->x_norm2 = h[1];
+  out->objective = 0.5 * h[2];
+  out->dg_norm2 = h[3];
+  out->rel_change = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] == 0.0 ? 0.0 : INFINITY);
+  out->sweeps_done = sweeps_done;
+  out->converged = 0;
+}
+
+ifctn_status job_close(ifctn_job* J) { return ifctn_destroy(J); }
+
+ifctn_status set_error(ifctn_status st, const char* msg) { return fail(st, "%s", msg); }
+
+}  // namespace ifctn
+
+extern "C" {
+
+ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
+                        const double* G0_host, void* stream, ifctn_job** out) {
+  return job_open(params, O_dev, mask_dev, G0_host, (hipStream_t)stream, nullptr, 0, true, out);
+}
+
 
 ifctn_status ifctn_sweep(ifctn_job* J, int32_t nsweeps, ifctn_stats* stats) {
   if (!J) return fail(IFCTN_E_INVAL, "job is NULL");
@@ -872,13 +947,7 @@ ifctn_status ifctn_sweep(ifctn_job* J, int32_t nsweeps, ifctn_stats* stats) {
     double h[5];
     HIPTRY(hipMemcpyAsync(h, J->stats5, sizeof(h), hipMemcpyDeviceToHost, J->stream));
     HIPTRY(hipStreamSynchronize(J->stream));
-    stats->dx_norm2 = h[0];
-    stats->x_norm2 = h[1];
-    stats->objective = 0.5 * h[2];
-    stats->dg_norm2 = h[3];
-    stats->rel_change = h[1] > 0.0 ? std::sqrt(h[0] / h[1]) : (h[0] == 0.0 ? 0.0 : INFINITY);
-    stats->sweeps_done = J->sweeps_done;
-    stats->converged = 0;
+    stats_from(h, J->sweeps_done, stats);
   }
   return IFCTN_OK;
 }

@@ -32,7 +32,8 @@ EXPORTED = [
     "ifctn_num_factor_entries", "ifctn_workspace_bytes", "ifctn_init", "ifctn_sweep",
     "ifctn_reconstruct", "ifctn_get_factors", "ifctn_destroy", "ifctn_complete",
     "ifctn_assemble", "ifctn_timing_enable", "ifctn_timing_query", "ifctn_last_error",
-    "ifctn_promote",
+    "ifctn_promote", "ifctn_server_create", "ifctn_server_submit", "ifctn_server_poll",
+    "ifctn_server_queued", "ifctn_server_destroy",
 ]
 
 
@@ -61,6 +62,40 @@ class IfctnStats(ctypes.Structure):
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class IfctnServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget_bytes", ctypes.c_size_t),
+        ("max_active", ctypes.c_int32),
+        ("num_streams", ctypes.c_int32),
+        ("sweeps_per_round", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+    ]
+
+
+class IfctnRequest(ctypes.Structure):
+    _fields_ = [
+        ("params", IfctnParams),
+        ("O_dev", ctypes.c_void_p),
+        ("mask_dev", ctypes.c_void_p),
+        ("G0_host", ctypes.POINTER(ctypes.c_double)),
+        ("t_max", ctypes.c_int32),
+        ("eps", ctypes.c_double),
+        ("X_out_dev", ctypes.c_void_p),
+        ("tag", ctypes.c_uint64),
+    ]
+
+
+class IfctnCompletion(ctypes.Structure):
+    _fields_ = [
+        ("tag", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("stats", IfctnStats),
+        ("t_submit", ctypes.c_double),
+        ("t_admit", ctypes.c_double),
+        ("t_done", ctypes.c_double),
+    ]
 
 
 class IfctnError(RuntimeError):
@@ -96,6 +131,11 @@ def lib():
         "ifctn_timing_query": (st, [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]),
         "ifctn_last_error": (ctypes.c_char_p, []),
         "ifctn_promote": (st, [vp]),
+        "ifctn_server_create": (st, [ctypes.POINTER(IfctnServerConfig), ctypes.POINTER(vp)]),
+        "ifctn_server_submit": (st, [vp, ctypes.POINTER(IfctnRequest)]),
+        "ifctn_server_poll": (st, [vp, ctypes.POINTER(IfctnCompletion), i32, ctypes.POINTER(i32), i32]),
+        "ifctn_server_queued": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
+        "ifctn_server_destroy": (st, [vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -233,3 +273,80 @@ def assemble(dims, ranks, G, precision=IFCTN_FP32):
     _check(lib().ifctn_assemble(ctypes.byref(params), _dptr(g), ctypes.c_void_p(out.data_ptr()),
                                 _stream_handle()))
     return out
+
+
+class Server:
+    """Continuous-batching server (ifctn_server_*): requests are admitted by
+    slots and HBM budget and overlap on the device.  Inputs are torch CUDA
+    tensors (or numpy arrays, copied to the device); the binding keeps them
+    and the output tensor alive until the completion is polled."""
+
+    def __init__(self, hbm_budget_bytes, max_active=8, num_streams=4, sweeps_per_round=10, device=None):
+        cfg = IfctnServerConfig()
+        cfg.hbm_budget_bytes = int(hbm_budget_bytes)
+        cfg.max_active, cfg.num_streams = int(max_active), int(num_streams)
+        cfg.sweeps_per_round = int(sweeps_per_round)
+        cfg.device = int(torch.cuda.current_device() if device is None else device)
+        h = ctypes.c_void_p()
+        _check(lib().ifctn_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.handle = h
+        self._live = {}
+        self._next = 0
+
+    def submit(self, O, mask, G0, dims, ranks, t_max, eps=0.0, rho=0.1, precision=IFCTN_FP32, refine_sweeps=0,
+               tag=None, sync=True):
+        dims = tuple(int(d) for d in dims)
+        params = make_params(dims, ranks, rho, 0.0, precision, refine_sweeps)
+        dt = _dtype(precision)
+        Ot = torch.as_tensor(O).to(device="cuda", dtype=dt).contiguous()
+        Mt = torch.as_tensor(np.asarray(mask, dtype=np.uint8) if isinstance(mask, np.ndarray) else mask)
+        Mt = Mt.to(device="cuda", dtype=torch.uint8).contiguous()
+        g0 = np.ascontiguousarray(workloads.pack(G0, dims, ranks) if isinstance(G0, dict) else G0,
+                                  dtype=np.float64)
+        out = torch.empty(dims, dtype=dt, device="cuda")
+        if tag is None:
+            tag = self._next
+        self._next = max(self._next, int(tag)) + 1
+        if sync:  # the server's streams do not wait for torch's
+            torch.cuda.current_stream().synchronize()
+        r = IfctnRequest()
+        r.params = params
+        r.O_dev, r.mask_dev = Ot.data_ptr(), Mt.data_ptr()
+        r.G0_host = _dptr(g0)
+        r.t_max, r.eps = int(t_max), float(eps)
+        r.X_out_dev = out.data_ptr()
+        r.tag = int(tag)
+        _check(lib().ifctn_server_submit(self.handle, ctypes.byref(r)))
+        self._live[int(tag)] = (Ot, Mt, out)
+        return int(tag)
+
+    def poll(self, max_n=64, wait_ms=0):
+        buf = (IfctnCompletion * max_n)()
+        n = ctypes.c_int32()
+        _check(lib().ifctn_server_poll(self.handle, buf, int(max_n), ctypes.byref(n), int(wait_ms)))
+        res = []
+        for q in range(n.value):
+            c = buf[q]
+            keep = self._live.pop(int(c.tag), None)
+            res.append({"tag": int(c.tag), "status": int(c.status), "stats": c.stats.as_dict(),
+                        "t_submit": c.t_submit, "t_admit": c.t_admit, "t_done": c.t_done,
+                        "X": keep[2] if keep else None})
+        return res
+
+    def queued(self):
+        a, b = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib().ifctn_server_queued(self.handle, ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().ifctn_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

@@ -291,3 +291,75 @@ def random_problem(dims, ranks, seed: int, keep: float = 0.5, rho: float = 0.1,
     rms = float(np.sqrt(np.mean(obs * obs))) if obs.size else 1.0
     G0 = initial_factors(rng, dims, ranks, rms)
     return Problem("random", dims, ranks, O, mask.astype(np.uint8), X, G0, rho, sweeps)
+
+
+# --------------------------------------------------------------------------
+# served mix: many completion requests with Poisson arrivals
+# --------------------------------------------------------------------------
+SERVED = dict(n=512, rate=200.0, orders=(3, 4, 5), size_lo=16, size_hi=256, cap=4194304,
+              ranks=(2, 3, 4, 5, 6), keeps=(0.05, 0.10, 0.30), t_max=100, eps=1e-5, noise=0.01)
+
+
+@dataclass
+class ServedSpec:
+    index: int
+    arrival: float            # seconds after the first arrival window opens
+    dims: tuple
+    ranks: np.ndarray
+    keep: float
+    seed: int                 # seed of this request's own tensors
+    planted: FactorDict       # N(0, 1) planted factors
+
+
+def served_dims(rng, N, lo, hi, cap):
+    """Mode sizes ~ U{lo..hi}; when the product exceeds the cap every mode is
+    scaled by (cap / product)^(1/N), floored, and kept >= lo."""
+    dims = [int(x) for x in rng.integers(lo, hi + 1, size=N)]
+    prod = math.prod(dims)
+    if prod > cap:
+        f = (cap / prod) ** (1.0 / N)
+        dims = [max(lo, int(math.floor(d * f))) for d in dims]
+        while math.prod(dims) > cap:          # floating-point edge: shave the largest mode
+            m = int(np.argmax(dims))
+            dims[m] -= 1
+    return tuple(dims)
+
+
+def served_requests(n=None, seed=0, **over):
+    """Shapes, ranks, sampling ratios, arrival times and planted factors of
+    the served mix (random draws only)."""
+    cfg = dict(SERVED)
+    cfg.update(over)
+    n = cfg["n"] if n is None else n
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for q in range(n):
+        t += float(rng.exponential(1.0 / cfg["rate"]))
+        N = int(rng.choice(cfg["orders"]))
+        dims = served_dims(rng, N, cfg["size_lo"], cfg["size_hi"], cfg["cap"])
+        R = int(rng.choice(cfg["ranks"]))
+        keep = float(rng.choice(cfg["keeps"]))
+        ranks = uniform_ranks(N, R)
+        rs = int(rng.integers(0, 2 ** 31 - 1))
+        planted = _draw_factors(np.random.default_rng(rs), dims, ranks, "normal")
+        out.append(ServedSpec(q, t, dims, ranks, keep, rs, planted))
+    return out
+
+
+def served_problem(spec: ServedSpec, core: np.ndarray) -> Problem:
+    """Finish one served request from its assembled planted tensor: unit max,
+    N(0, 0.01^2) noise, Bernoulli(keep) mask, initial factors."""
+    rng = np.random.default_rng(spec.seed + 1)
+    X = np.asarray(core, dtype=np.float64).reshape(spec.dims)
+    X = X / np.max(np.abs(X))
+    X = X + rng.normal(0.0, SERVED["noise"], size=spec.dims)
+    mask = rng.random(spec.dims) < spec.keep
+    X32 = X.astype(np.float32)
+    O = np.where(mask, X32, np.float32(0.0)).astype(np.float32)
+    obs = X32[mask].astype(np.float64)
+    rms = float(np.sqrt(np.mean(obs * obs))) if obs.size else 1.0
+    G0 = initial_factors(rng, spec.dims, spec.ranks, rms)
+    return Problem(f"served{spec.index}", spec.dims, spec.ranks, O, mask.astype(np.uint8), X32, G0, 0.1,
+                   SERVED["t_max"])
+

@@ -48,3 +48,41 @@ def test_workspace_fits_every_workload():
     for name, (dims, R, _) in W.CONFIGS.items():
         b = ifctn.workspace_bytes(dims, W.uniform_ranks(len(dims), R))
         assert 0 < b < 64 << 20, (name, b)
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """The ctypes mirrors of the header's structs have the C layout (sizes
+    and field offsets from a C program compiled against include/ifctn.h)."""
+    import ctypes
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {
+        "ifctn_params": ("IfctnParams", ["order", "dims", "ranks", "rho", "rho_x", "precision", "refine_sweeps"]),
+        "ifctn_stats": ("IfctnStats", ["rel_change", "objective", "x_norm2", "dx_norm2", "dg_norm2",
+                                       "sweeps_done", "converged"]),
+        "ifctn_server_config": ("IfctnServerConfig", ["hbm_budget_bytes", "max_active", "num_streams",
+                                                      "sweeps_per_round", "device"]),
+        "ifctn_request": ("IfctnRequest", ["params", "O_dev", "mask_dev", "G0_host", "t_max", "eps",
+                                           "X_out_dev", "tag"]),
+        "ifctn_completion": ("IfctnCompletion", ["tag", "status", "stats", "t_submit", "t_admit", "t_done"]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ifctn.h"', "int main(void) {"]
+    for cname, (_, fl) in fields.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in fl:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.split() for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                  check=True).stdout.splitlines())
+    for cname, (pyname, fl) in fields.items():
+        cls = getattr(ifctn, pyname)
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f in fl:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
