@@ -35,6 +35,13 @@ def parse():
                     help="bf16 = bfloat16 X streaming + float32 refinement sweeps (BF16_REFINE)")
     ap.add_argument("--refine", type=int, default=30, help="float32 refinement sweeps of the bf16 path")
     ap.add_argument("--no-compare", action="store_true", help="skip the bf16-vs-fp32 equal-RSE comparison")
+    ap.add_argument("--no-serve", action="store_true", help="skip the served-mix leg")
+    ap.add_argument("--serve-requests", type=int, default=512)
+    ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16"])
+    ap.add_argument("--serve-budget-gb", type=float, default=64.0)
+    ap.add_argument("--serve-slots", type=int, default=16)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-round", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=0, help="oracle sweeps (0 = auto, ~10-30 s)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -164,6 +171,81 @@ def precision_comparison(ifctn, torch, p, steps, refine):
             "speedup_bf16_over_fp32": round(ms32 / msb, 4)}
 
 
+def served_inputs(ifctn, torch, specs):
+    """Device tensors of the served mix: planted part assembled by the library,
+    unit max, N(0, 0.01^2) noise and Bernoulli masks from torch's device
+    generator (seeded per request), initial factors from numpy."""
+    from paper_2511_16358_amd import workloads as W
+    out = []
+    for sp in specs:
+        core = ifctn.assemble(sp.dims, sp.ranks, sp.planted)                 # float32 on the device
+        g = torch.Generator(device="cuda")
+        g.manual_seed(sp.seed)
+        X = core / core.abs().max()
+        X = X + W.SERVED["noise"] * torch.randn(sp.dims, device="cuda", generator=g)
+        mask = (torch.rand(sp.dims, device="cuda", generator=g) < sp.keep).to(torch.uint8)
+        O = torch.where(mask.bool(), X, torch.zeros((), device="cuda"))
+        obs = X[mask.bool()].double()
+        rms = float(torch.sqrt((obs * obs).mean())) if obs.numel() else 1.0
+        G0 = W.initial_factors(np.random.default_rng(sp.seed + 1), sp.dims, sp.ranks, rms)
+        out.append((O.contiguous(), mask.contiguous(), G0))
+    torch.cuda.synchronize()
+    return out
+
+
+def serve_mix(ifctn, torch, args):
+    """The served mix: requests submitted at their Poisson arrival times to a
+    continuous-batching server; latency = completion - submission."""
+    from paper_2511_16358_amd import workloads as W
+    specs = W.served_requests(args.serve_requests, seed=0)
+    t_gen = time.perf_counter()
+    inputs = served_inputs(ifctn, torch, specs)
+    t_gen = time.perf_counter() - t_gen
+    prec = ifctn.IFCTN_BF16_REFINE if args.serve_precision == "bf16" else ifctn.IFCTN_FP32
+    refine = 30 if prec == ifctn.IFCTN_BF16_REFINE else 0
+    srv = ifctn.Server(int(args.serve_budget_gb * (1 << 30)), max_active=args.serve_slots,
+                       num_streams=args.serve_streams, sweeps_per_round=args.serve_round)
+    done = {}
+    t0 = time.perf_counter()
+    for q, (sp, (O, M, G0)) in enumerate(zip(specs, inputs)):
+        while time.perf_counter() - t0 < sp.arrival:
+            for c in srv.poll(64):
+                done[c["tag"]] = c
+            time.sleep(0.0002)
+        srv.submit(O, M, G0, sp.dims, sp.ranks, W.SERVED["t_max"], eps=W.SERVED["eps"], precision=prec,
+                   refine_sweeps=refine, tag=q, sync=False)
+    while len(done) < len(specs):
+        for c in srv.poll(64, wait_ms=200):
+            done[c["tag"]] = c
+    wall = time.perf_counter() - t0
+    srv.close()
+    bad = [c for c in done.values() if c["status"] != ifctn.IFCTN_OK]
+    lat = np.array([c["t_done"] - c["t_submit"] for c in done.values()])
+    queue = np.array([c["t_admit"] - c["t_submit"] for c in done.values()])
+    sweeps = sum(c["stats"]["sweeps_done"] for c in done.values())
+    first = min(c["t_submit"] for c in done.values())
+    last = max(c["t_done"] for c in done.values())
+    nX = np.array([np.prod(sp.dims) for sp in specs], dtype=np.float64)
+    return {"requests": len(specs), "failed": len(bad),
+            "p50_latency_ms": round(1e3 * float(np.percentile(lat, 50)), 2),
+            "p99_latency_ms": round(1e3 * float(np.percentile(lat, 99)), 2),
+            "mean_queue_ms": round(1e3 * float(queue.mean()), 2),
+            "aggregate_sweeps_per_s": round(sweeps / (last - first), 1),
+            "entry_sweeps_per_s": round(float(sum(nX[c["tag"]] * c["stats"]["sweeps_done"]
+                                                  for c in done.values())) / (last - first), 1),
+            "converged": int(sum(c["stats"]["converged"] for c in done.values())),
+            "makespan_s": round(last - first, 3), "wall_s": round(wall, 3),
+            "arrival_window_s": round(specs[-1].arrival, 3),
+            "mean_entries": int(nX.mean()),
+            "precision": args.serve_precision + ("+30 fp32 refine" if refine else ""),
+            "server": {"hbm_budget_gb": args.serve_budget_gb, "slots": args.serve_slots,
+                       "streams": args.serve_streams, "sweeps_per_round": args.serve_round},
+            "input_generation_s": round(t_gen, 2),
+            "mix": "512 requests, Poisson arrivals at 200/s, orders 3-5, modes 16-256 (<= 4,194,304 entries), "
+                   "R in 2..6, sampling 5/10/30%, planted iFCTN N(0,1) unit max + N(0,0.01^2), "
+                   "t_max 100, eps 1e-5"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -243,6 +325,10 @@ def main():
     if not args.no_compare and args.precision != "fp64":
         cmp = precision_comparison(ifctn, torch, p, W.CONFIGS[args.workload][2], args.refine)
 
+    served = None
+    if not args.no_serve:
+        served = serve_mix(ifctn, torch, args)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(args.workload, 0, args.cpu_sweeps)
@@ -268,6 +354,7 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
         "precision_comparison": cmp,
+        "serving": served,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per.items()},
         "dominant_kernel_class": dominant,
         "rse_after_timed_sweeps": rse,
