@@ -221,6 +221,16 @@ ifctn_status ifctn_server_queued(ifctn_server* server, int32_t* queued, int32_t*
  * release everything (NULL is accepted). */
 ifctn_status ifctn_server_destroy(ifctn_server* server);
 
+/* Process-wide tuning option, read when a job is created:
+ *   "phased_min": a factor block uses the phased form (partial Gram matrices
+ *   over ranges of the Gram weight set on many workgroups, then one
+ *   workgroup per column for the solve) when one of its Gram weight sets
+ *   holds at least this many entries; the one-workgroup-per-column form
+ *   otherwise.  Both give the same solution of eq. (updateG) up to rounding.
+ *   value < 0 restores the default (16384).
+ * Unknown names: IFCTN_E_INVAL. */
+ifctn_status ifctn_set_option(const char* name, int64_t value);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char* ifctn_last_error(void);
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -427,6 +428,7 @@ struct ifctn_job {
   double* Q = nullptr;
   double* Upart = nullptr;
   double* Ufin = nullptr;
+  double* Hpart = nullptr;
   double* normpart = nullptr;
   double* dgpart = nullptr;
   double* stats5 = nullptr;
@@ -434,6 +436,8 @@ struct ifctn_job {
   ContractPlan cplan[MAXN];
   QArgs qplan[MAXN];
   SolveArgs splan[MAXN];
+  bool phased[MAXN] = {};
+  PhaseArgs pplan[MAXN][MAXN - 1];
   int nnorm = 0, ndg = 0;
   bool pending = false;
   int sweeps_done = 0;
@@ -449,8 +453,32 @@ struct ifctn_job {
 namespace {
 
 struct Sizes {
-  size_t x, xb, bits, G, W64, Wc, Q, Upart, Ufin, normpart, dgpart, stats, flag, qitems, total;
+  size_t x, xb, bits, G, W64, Wc, Q, Upart, Ufin, Hpart, normpart, dgpart, stats, flag, qitems, total;
 };
+
+// A factor block takes the phased form when one of its Gram weight sets is
+// large: the one-workgroup-per-column kernel would stream all of Q_{k,i}
+// through each of only I_k workgroups.
+constexpr long long kPhasedMinDefault = 16384;
+std::atomic<long long> g_phased_min{-1};
+
+long long phased_min() {
+  long long v = g_phased_min.load();
+  return v >= 0 ? v : kPhasedMinDefault;
+}
+
+bool use_phased(const Geo& g, const QArgs& Q, int k) {
+  long long m = 0;
+  for (int t = 0; t < g.N - 1; ++t) m = std::max(m, Q.it[t].D * (long long)(Q.it[t].R * (Q.it[t].R + 1) / 2));
+  (void)k;
+  return m >= phased_min();
+}
+
+int hp_width(int Ik) {
+  int w = 1;
+  while (w < Ik && w < HP_JW) w <<= 1;
+  return w;
+}
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
@@ -462,7 +490,7 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
   s.G = al256(g.nG * 8);
   s.W64 = al256(g.nW * 8);
   s.Wc = al256(g.nW * g.esz);
-  long long qmax = 0, upmax = 0, ufmax = 0, nnorm = 0, ndg = 0;
+  long long qmax = 0, upmax = 0, ufmax = 0, hmax = 0, nnorm = 0, ndg = 0;
   const bool dbg = std::getenv("IFCTN_DEBUG_PLAN") != nullptr;
   for (int k = 0; k < g.N; ++k) {
     ContractPlan P = plan_contract(g, k);
@@ -483,18 +511,25 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
     qmax = std::max(qmax, qs);
     upmax = std::max(upmax, (long long)P.a.S * P.a.FS * P.a.Ik * P.a.Rprod);
     ufmax = std::max(ufmax, (long long)P.a.Ik * P.a.Rprod);
+    if (use_phased(g, Q, k))
+      for (int t = 0; t < g.N - 1; ++t) {
+        const long long ks = (Q.it[t].D + HP_DC - 1) / HP_DC;
+        hmax = std::max(hmax, ks * g.dims[k] * (long long)(Q.it[t].R * (Q.it[t].R + 1) / 2));
+      }
     if (k == 0) nnorm = (long long)P.a.JT * P.a.S * P.a.FS;
     ndg += (long long)(g.N - 1) * g.dims[k];
   }
   s.Q = al256(qmax * 8);
   s.Upart = al256(upmax * 8);
   s.Ufin = al256(ufmax * 8);
+  s.Hpart = al256(hmax * 8);
   s.normpart = al256(nnorm * 3 * 8);
   s.dgpart = al256(ndg * 8);
   s.stats = al256(8 * 8);
   s.flag = al256(16);
   s.qitems = al256(sizeof(QItem) * MAXN * (MAXN - 1));
-  s.total = s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.normpart + s.dgpart + s.stats + s.flag +
+  s.total = s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.Hpart + s.normpart + s.dgpart +
+            s.stats + s.flag +
             s.qitems;
   return s;
 }
@@ -569,6 +604,33 @@ void build_solve_plans(ifctn_job* J) {
       B.w_sy = w.s2;
       ++t;
     }
+    J->phased[k] = use_phased(g, Q, k);
+    for (int t2 = 0; t2 < a.nsub; ++t2) {
+      PhaseArgs& h = J->pplan[k][t2];
+      std::memset(&h, 0, sizeof(h));
+      h.B = a.sb[t2];
+      h.t = t2;
+      h.k = k;
+      h.Ik = a.Ik;
+      h.nu = a.nu;
+      h.Rprod = a.Rprod;
+      h.rho = a.rho;
+      for (int u = 0; u < a.nu; ++u) {
+        h.urank[u] = a.urank[u];
+        h.ustride[u] = a.ustride[u];
+        h.ugoff[u] = a.ugoff[u];
+      }
+      for (int c = 0; c < h.B.nd; ++c) h.edm[c] = a.ekm[h.B.dt[c]];
+      h.JW = hp_width(a.Ik);
+      h.JT = (a.Ik + h.JW - 1) / h.JW;
+      h.KS = (int)((h.B.D + HP_DC - 1) / HP_DC);
+      h.Ufin = J->Ufin;
+      h.Hpart = J->Hpart;
+      h.W64 = J->W64;
+      h.Wc = J->Wc;
+      h.G = J->G;
+      h.dgpart = a.dgpart;
+    }
   }
   J->ndg = (int)dgo;
 }
@@ -613,7 +675,14 @@ hipError_t do_gram(ifctn_job* J, const void* c) { return launch_q(*(const QArgs*
 
 hipError_t do_solve(ifctn_job* J, const void* c) {
   const SolveArgs* a = (const SolveArgs*)c;
-  return launch_solve(J->g.dtype, *a, J->stream);
+  const int k = a->k;
+  if (!J->phased[k]) return launch_solve(J->g.dtype, *a, J->stream);
+  hipError_t e = launch_urow(*a, J->Ufin, J->stream);
+  for (int t = 0; t < a->nsub && e == hipSuccess; ++t) {
+    e = launch_hpart(J->pplan[k][t], J->stream);
+    if (e == hipSuccess) e = launch_solve_col(J->g.dtype, J->pplan[k][t], J->stream);
+  }
+  return e;
 }
 
 hipError_t run_sweep(ifctn_job* J) {
@@ -811,6 +880,7 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   J->Q = (double*)p;             p += s.Q;
   J->Upart = (double*)p;         p += s.Upart;
   J->Ufin = (double*)p;          p += s.Ufin;
+  J->Hpart = (double*)p;         p += s.Hpart;
   J->normpart = (double*)p;      p += s.normpart;
   J->dgpart = (double*)p;        p += s.dgpart;
   J->stats5 = (double*)p;        p += s.stats;
@@ -834,10 +904,15 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   }
   J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
   build_solve_plans(J);
-  for (int k = 0; k < g.N; ++k) J->splan[k].stop = J->flag + 1;
   for (int k = 0; k < g.N; ++k) {
-    if (solve_smem_bytes(J->splan[k]) > kMaxLds) {
-      (void)hipFree(J->arena);
+    J->splan[k].stop = J->flag + 1;
+    for (int t = 0; t < g.N - 1; ++t) J->pplan[k][t].stop = J->flag + 1;
+  }
+  for (int k = 0; k < g.N; ++k) {
+    const bool too_big = J->phased[k] ? (size_t)J->splan[k].Rprod * 8 > kMaxLds
+                                      : solve_smem_bytes(J->splan[k]) > kMaxLds;
+    if (too_big) {
+      if (J->own_arena) (void)hipFree(J->arena);
       delete J;
       return fail(IFCTN_E_UNSUPPORTED, "mode sizes too large for the factor-block kernel (mode %d)", k);
     }
@@ -1046,6 +1121,15 @@ ifctn_status ifctn_assemble(const ifctn_params* params, const double* G_host, vo
   (void)hipFree(buf);
   if (e != hipSuccess) return fail(IFCTN_E_HIP, "assemble: %s", hipGetErrorString(e));
   return IFCTN_OK;
+}
+
+ifctn_status ifctn_set_option(const char* name, int64_t value) {
+  if (!name) return fail(IFCTN_E_INVAL, "name is NULL");
+  if (std::strcmp(name, "phased_min") == 0) {
+    g_phased_min.store(value < 0 ? -1 : (long long)value);
+    return IFCTN_OK;
+  }
+  return fail(IFCTN_E_INVAL, "unknown option '%s'", name);
 }
 
 ifctn_status ifctn_timing_enable(ifctn_job* J, int32_t enable) {

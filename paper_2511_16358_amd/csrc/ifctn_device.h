@@ -813,7 +813,8 @@ extern thread_local bool tl_ev_used;
 #define IFCTN_GO(kern, grid, blk, smem, s, ...)                                                   \
   do {                                                                                            \
     if (tl_ev_start) {                                                                            \
-      hipExtLaunchKernelGGL(kern, grid, blk, smem, s, tl_ev_start, tl_ev_stop, 0u, __VA_ARGS__);  \
+      hipExtLaunchKernelGGL(kern, grid, blk, smem, s, tl_ev_used ? nullptr : tl_ev_start,          \
+                            tl_ev_stop, 0u, __VA_ARGS__);                                          \
       tl_ev_used = true;                                                                          \
     } else {                                                                                      \
       hipLaunchKernelGGL(kern, grid, blk, smem, s, __VA_ARGS__);                                  \

@@ -148,6 +148,34 @@ struct SolveArgs {
   const int* stop;               // device stop flag
 };
 
+// Phased factor block, for blocks whose Gram weight sets are large (many d):
+// per sub-block, k_hpart forms partial H_j over ranges of d for a tile of
+// columns (the Q range and the weights staged in LDS, Q read once per tile),
+// then k_solve_col reduces the partials of column j in a fixed order, forms
+// b_j, solves and refreshes row j of W_{k,i}.  The Gauss-Seidel order over i
+// is kept by launching the sub-blocks one after another.
+constexpr int HP_JW = 32;     // max columns per k_hpart workgroup (power of two)
+constexpr int HP_DC = 112;    // d per k_hpart workgroup
+
+struct PhaseArgs {
+  SubBlock B;
+  int t;                      // sub-block index (row of the block's dgpart)
+  int k, Ik, nu, Rprod;
+  double rho;
+  int urank[MAXN - 1];
+  long long ustride[MAXN - 1];
+  long long ugoff[MAXN - 1];
+  EdgeRef edm[MAXC];          // W_{k,m}(j, i_m) for the d-modes of this sub-block
+  int JW, JT, KS;             // column tile, column tiles, d ranges
+  const double* Ufin;         // [Ik][Rprod]
+  double* Hpart;              // [KS][Ik][np]
+  double* W64;
+  void* Wc;
+  double* G;
+  double* dgpart;             // the block's [nsub][Ik]
+  const int* stop;
+};
+
 struct ReconArgs {
   int N;
   int dims[MAXN];
@@ -185,6 +213,10 @@ void set_kernel_events(hipEvent_t start, hipEvent_t stop);
 bool kernel_events_used();
 hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s);
 size_t solve_smem_bytes(const SolveArgs& a);
+// phased factor block: U rows into Ufin, then per sub-block k_hpart + k_solve_col
+hipError_t launch_urow(const SolveArgs& a, double* Ufin, hipStream_t s);
+hipError_t launch_hpart(const PhaseArgs& a, hipStream_t s);
+hipError_t launch_solve_col(int dtype, const PhaseArgs& a, hipStream_t s);
 hipError_t launch_reconstruct(int dtype, const ReconArgs& a, hipStream_t s);
 // Stop test of Algorithm 1 on the device, after an X step: reduces the
 // partial norms like launch_finalize and, unless state[0] (stop flag) is

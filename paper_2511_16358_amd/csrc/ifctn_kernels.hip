@@ -259,6 +259,52 @@ __host__ __device__ inline size_t solve_layout(const SolveArgs& a, size_t* o_u, 
   return o;
 }
 
+// U_k row j: the split partials reduced in a fixed order (part: NT doubles of LDS)
+__device__ __forceinline__ void urow_reduce(const SolveArgs& a, int j, double* part, double* u) {
+  const int tid = threadIdx.x, Ik = a.Ik;
+  if (a.Rprod < NT) {
+    const int nch = min(a.S, NT / a.Rprod);
+    const int col = tid % a.Rprod, c = tid / a.Rprod;
+    double v = 0.0;
+    if (c < nch) {
+      const double* up = a.Upart + (long long)j * a.Rprod + col;
+      const long long stride = (long long)Ik * a.Rprod;
+      int q = c;
+      for (; q + 15 * nch < a.S; q += 16 * nch) {
+        double x[16];
+#pragma unroll
+        for (int w = 0; w < 16; ++w) x[w] = up[(long long)(q + w * nch) * stride];
+#pragma unroll
+        for (int w = 0; w < 16; ++w) v += x[w];
+      }
+      for (; q < a.S; q += nch) v += up[(long long)q * stride];
+    }
+    part[tid] = v;
+    __syncthreads();
+    if (tid < a.Rprod) {
+      double sum = 0.0;
+      for (int q = 0; q < nch; ++q) sum += part[q * a.Rprod + tid];
+      u[tid] = sum;
+    }
+  } else {
+    for (int col = tid; col < a.Rprod; col += NT) {
+      const double* up = a.Upart + (long long)j * a.Rprod + col;
+      const long long stride = (long long)Ik * a.Rprod;
+      double sum = 0.0;
+      int q = 0;
+      for (; q + 7 < a.S; q += 8) {
+        double x[8];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) x[w] = up[(long long)(q + w) * stride];
+#pragma unroll
+        for (int w = 0; w < 8; ++w) sum += x[w];
+      }
+      for (; q < a.S; ++q) sum += up[(long long)q * stride];
+      u[col] = sum;
+    }
+  }
+}
+
 template <typename TC>
 __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   if (a.stop && *a.stop) return;
@@ -295,38 +341,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
     const int t = e / MAXR, r = e - t * MAXR;
     gk[e] = r < a.urank[t] ? G[a.ugoff[t] + (long long)r * Ik + j] : 0.0;
   }
-  // U_k row j: the split partials reduced in a fixed order
-  if (a.Rprod < NT) {
-    const int nch = min(a.S, NT / a.Rprod);
-    const int col = tid % a.Rprod, c = tid / a.Rprod;
-    double v = 0.0;
-    if (c < nch) {
-      const double* up = a.Upart + (long long)j * a.Rprod + col;
-      const long long stride = (long long)Ik * a.Rprod;
-      int q = c;
-      for (; q + 15 * nch < a.S; q += 16 * nch) {
-        double x[16];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) x[u] = up[(long long)(q + u * nch) * stride];
-#pragma unroll
-        for (int u = 0; u < 16; ++u) v += x[u];
-      }
-      for (; q < a.S; q += nch) v += up[(long long)q * stride];
-    }
-    part[tid] = v;
-    __syncthreads();
-    if (tid < a.Rprod) {
-      double sum = 0.0;
-      for (int q = 0; q < nch; ++q) sum += part[q * a.Rprod + tid];
-      u[tid] = sum;
-    }
-  } else {
-    for (int col = tid; col < a.Rprod; col += NT) {
-      double sum = 0.0;
-      for (int q = 0; q < a.S; ++q) sum += a.Upart[((long long)q * Ik + j) * a.Rprod + col];
-      u[col] = sum;
-    }
-  }
+  urow_reduce(a, j, part, u);
   __syncthreads();
 
   for (int t = 0; t < a.nsub; ++t) {
@@ -457,6 +472,198 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       Wc[ad] = (TC)sum;
     }
     __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------------
+// K5, phased form (large Gram weight sets)
+// --------------------------------------------------------------------------
+// U_k rows into Ufin (once per block)
+__global__ __launch_bounds__(NT) void k_urow(SolveArgs a, double* __restrict__ Ufin) {
+  if (a.stop && *a.stop) return;
+  __shared__ double part[NT];
+  extern __shared__ double urow[];
+  const int j = blockIdx.x;
+  urow_reduce(a, j, part, urow);
+  __syncthreads();
+  for (int c = threadIdx.x; c < a.Rprod; c += NT) Ufin[(long long)j * a.Rprod + c] = urow[c];
+}
+
+// Partial H_j(p) = sum_{d in range} w_j(d) Q(d, p) for a tile of columns.
+template <int R>
+__global__ __launch_bounds__(NT) void k_hpart(PhaseArgs a) {
+  if (a.stop && *a.stop) return;
+  constexpr int NP = R * (R + 1) / 2;
+  __shared__ double sm[HP_JW * HP_DC + HP_DC * MAXP];
+  double* wL = sm;                       // [jcnt][dn] weights
+  double* qL = sm + HP_JW * HP_DC;       // [dn][NP] Gram weight entries
+  const int tid = threadIdx.x;
+  const int jt = blockIdx.x % a.JT, ks = blockIdx.x / a.JT;
+  const int JW = a.JW;
+  const int j0 = jt * JW, jcnt = min(JW, a.Ik - j0);
+  const long long dlo = (long long)ks * HP_DC;
+  const int dn = (int)min((long long)HP_DC, a.B.D - dlo);
+  const double* __restrict__ Q = a.B.Q + dlo * NP;
+  for_batched<4>(dn * NP, [&](int e) { return Q[e]; }, [&](int e, double v) { qL[e] = v; });
+  const int nd = a.B.nd;
+  for_batched<2>(
+      jcnt * dn,
+      [&](int e) {
+        const int jl = e / dn;
+        long long x = dlo + (e - jl * dn);
+        double w = 1.0;
+#pragma unroll
+        for (int c = MAXC - 1; c >= 0; --c) {
+          if (c < nd) {
+            const int dim = a.B.ddim[c];
+            const long long xq = x / dim;
+            const double v = a.W64[eaddr(a.edm[c], j0 + jl, x - xq * dim)];
+            x = xq;
+            w *= v * v;
+          }
+        }
+        return w;
+      },
+      [&](int e, double w) { wL[e] = w; });
+  __syncthreads();
+  const int DS = NT / JW;
+  const int jl = tid % JW, ds = tid / JW;
+  double h[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) h[p] = 0.0;
+  if (jl < jcnt) {
+    for (int dd = ds; dd < dn; dd += DS) {
+      const double w = wL[jl * dn + dd];
+      const double* q = qL + dd * NP;
+#pragma unroll
+      for (int p = 0; p < NP; ++p) h[p] += w * q[p];
+    }
+  }
+  // lanes of one column within a wave (offsets JW, 2 JW, ... < 64), fixed butterfly
+  for (int o = JW; o < 64; o <<= 1) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) h[p] += __shfl_xor(h[p], o, 64);
+  }
+  __syncthreads();                       // wL and qL are free again
+  double* red = sm;                      // [NT / 64][JW][NP]
+  const int wv = tid >> 6, lane = tid & 63;
+  if (lane < JW) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) red[(wv * JW + lane) * NP + p] = h[p];
+  }
+  __syncthreads();
+  for (int e = tid; e < jcnt * NP; e += NT) {
+    const int j2 = e / NP, p = e - j2 * NP;
+    double v = 0.0;
+    for (int w = 0; w < NT / 64; ++w) v += red[(w * JW + j2) * NP + p];
+    a.Hpart[((long long)ks * a.Ik + j0 + j2) * NP + p] = v;
+  }
+}
+
+// Column j of G_{k,i}: reduce the partial H_j, form b_j, solve, refresh W_{k,i}(j, :).
+template <typename TC>
+__global__ __launch_bounds__(NT) void k_solve_col(PhaseArgs a) {
+  if (a.stop && *a.stop) return;
+  __shared__ double part[NT], partb[NT];
+  __shared__ double Hs[MAXP], bs[MAXR], gold[MAXR], gnew[MAXR];
+  __shared__ double gk[(MAXN - 1) * MAXR];
+  const int tid = threadIdx.x, j = blockIdx.x, Ik = a.Ik;
+  const SubBlock& B = a.B;
+  const int R = B.R, np = B.np;
+  double* G = a.G;
+  for (int e = tid; e < a.nu * MAXR; e += NT) {
+    const int t = e / MAXR, r = e - t * MAXR;
+    gk[e] = r < a.urank[t] ? G[a.ugoff[t] + (long long)r * Ik + j] : 0.0;
+  }
+  // far-side factor for the refresh, issued early
+  const double* Gik = G + B.goff_ik;
+  double gpre[MAXR];
+  {
+    const int y = min(tid, B.Ii - 1);
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) gpre[r] = r < R ? Gik[(long long)r * B.Ii + y] : 0.0;
+  }
+  // H_j: thread (p, c) sums the ranges ks = c mod cpp in ascending order
+  const int cpp = NT / np;
+  const int p_me = tid % np, c_me = tid / np;
+  double hacc = 0.0;
+  if (c_me < cpp) {
+    const double* hp = a.Hpart + (long long)j * np + p_me;
+    const long long stride = (long long)Ik * np;
+    int q = c_me;
+    for (; q + 7 * cpp < a.KS; q += 8 * cpp) {
+      double x[8];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) x[w] = hp[(long long)(q + w * cpp) * stride];
+#pragma unroll
+      for (int w = 0; w < 8; ++w) hacc += x[w];
+    }
+    for (; q < a.KS; q += cpp) hacc += hp[(long long)q * stride];
+  }
+  __syncthreads();                       // gk complete
+  const int cpr = NT / R;
+  const int r_me = tid % R, cb = tid / R;
+  const int nother = a.Rprod / R;
+  double bacc = 0.0;
+  if (cb < cpr) {
+    const double* u = a.Ufin + (long long)j * a.Rprod;
+    for (int o = cb; o < nother; o += cpr) {
+      int rem = o;
+      long long col = (long long)r_me * a.ustride[B.upos];
+      double coef = 1.0;
+      for (int q = a.nu - 1; q >= 0; --q) {
+        if (q == B.upos) continue;
+        const int r = rem % a.urank[q];
+        rem /= a.urank[q];
+        col += (long long)r * a.ustride[q];
+        coef *= gk[q * MAXR + r];
+      }
+      bacc += coef * u[col];
+    }
+  }
+  part[tid] = (c_me < cpp) ? hacc : 0.0;
+  partb[tid] = (cb < cpr) ? bacc : 0.0;
+  __syncthreads();
+  if (tid < np) {
+    double sum = 0.0;
+    for (int c = 0; c < cpp; ++c) sum += part[c * np + tid];
+    Hs[tid] = sum;
+  } else if (tid >= 64 && tid < 64 + R) {
+    const int r = tid - 64;
+    double sum = 0.0;
+    for (int c = 0; c < cpr; ++c) sum += partb[c * R + r];
+    gold[r] = gk[B.upos * MAXR + r];
+    bs[r] = sum + a.rho * gold[r];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double dg = 0.0;
+    switch (R) {
+      case 1: dg = ldlt_solve<1>(Hs, bs, a.rho, gold, gnew); break;
+      case 2: dg = ldlt_solve<2>(Hs, bs, a.rho, gold, gnew); break;
+      case 3: dg = ldlt_solve<3>(Hs, bs, a.rho, gold, gnew); break;
+      case 4: dg = ldlt_solve<4>(Hs, bs, a.rho, gold, gnew); break;
+      case 5: dg = ldlt_solve<5>(Hs, bs, a.rho, gold, gnew); break;
+      case 6: dg = ldlt_solve<6>(Hs, bs, a.rho, gold, gnew); break;
+      case 7: dg = ldlt_solve<7>(Hs, bs, a.rho, gold, gnew); break;
+      default: dg = ldlt_solve<8>(Hs, bs, a.rho, gold, gnew); break;
+    }
+    for (int r = 0; r < R; ++r) G[B.goff_ki + (long long)r * Ik + j] = gnew[r];
+    a.dgpart[(long long)a.t * Ik + j] = dg;
+  }
+  __syncthreads();
+  TC* Wc = (TC*)a.Wc;
+  for (int y = tid; y < B.Ii; y += NT) {
+    double gv[MAXR];
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r) gv[r] = y < NT ? gpre[r] : (r < R ? Gik[(long long)r * B.Ii + y] : 0.0);
+    double sum = 0.0;
+#pragma unroll
+    for (int r = 0; r < MAXR; ++r)
+      if (r < R) sum += gnew[r] * gv[r];
+    const long long ad = B.w_off + (long long)j * B.w_sj + (long long)y * B.w_sy;
+    a.W64[ad] = sum;
+    Wc[ad] = (TC)sum;
   }
 }
 
@@ -612,6 +819,34 @@ hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s) {
     IFCTN_GO(k_solve<float>, dim3((unsigned)a.Ik), dim3(NT), smem, s, a);
   else
     IFCTN_GO(k_solve<double>, dim3((unsigned)a.Ik), dim3(NT), smem, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_urow(const SolveArgs& a, double* Ufin, hipStream_t s) {
+  IFCTN_GO(k_urow, dim3((unsigned)a.Ik), dim3(NT), (size_t)a.Rprod * 8, s, a, Ufin);
+  return hipGetLastError();
+}
+
+hipError_t launch_hpart(const PhaseArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)(a.JT * a.KS)), blk(NT);
+  switch (a.B.R) {
+    case 1: IFCTN_GO(k_hpart<1>, grid, blk, 0, s, a); break;
+    case 2: IFCTN_GO(k_hpart<2>, grid, blk, 0, s, a); break;
+    case 3: IFCTN_GO(k_hpart<3>, grid, blk, 0, s, a); break;
+    case 4: IFCTN_GO(k_hpart<4>, grid, blk, 0, s, a); break;
+    case 5: IFCTN_GO(k_hpart<5>, grid, blk, 0, s, a); break;
+    case 6: IFCTN_GO(k_hpart<6>, grid, blk, 0, s, a); break;
+    case 7: IFCTN_GO(k_hpart<7>, grid, blk, 0, s, a); break;
+    default: IFCTN_GO(k_hpart<8>, grid, blk, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_col(int dtype, const PhaseArgs& a, hipStream_t s) {
+  if (dtype == 0)
+    IFCTN_GO(k_solve_col<float>, dim3((unsigned)a.Ik), dim3(NT), 0, s, a);
+  else
+    IFCTN_GO(k_solve_col<double>, dim3((unsigned)a.Ik), dim3(NT), 0, s, a);
   return hipGetLastError();
 }
 

@@ -33,7 +33,7 @@ EXPORTED = [
     "ifctn_reconstruct", "ifctn_get_factors", "ifctn_destroy", "ifctn_complete",
     "ifctn_assemble", "ifctn_timing_enable", "ifctn_timing_query", "ifctn_last_error",
     "ifctn_promote", "ifctn_server_create", "ifctn_server_submit", "ifctn_server_poll",
-    "ifctn_server_queued", "ifctn_server_destroy",
+    "ifctn_server_queued", "ifctn_server_destroy", "ifctn_set_option",
 ]
 
 
@@ -136,6 +136,7 @@ def lib():
         "ifctn_server_poll": (st, [vp, ctypes.POINTER(IfctnCompletion), i32, ctypes.POINTER(i32), i32]),
         "ifctn_server_queued": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "ifctn_server_destroy": (st, [vp]),
+        "ifctn_set_option": (st, [ctypes.c_char_p, ctypes.c_int64]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -160,6 +161,11 @@ def make_params(dims, ranks, rho=0.1, rho_x=0.0, precision=IFCTN_FP32, refine_sw
             p.ranks[a][b] = int(ranks[a][b]) if a != b else 0
     p.rho, p.rho_x, p.precision, p.refine_sweeps = float(rho), float(rho_x), int(precision), int(refine_sweeps)
     return p
+
+
+def set_option(name: str, value: int):
+    """Process-wide tuning option (ifctn_set_option); value < 0 = default."""
+    _check(lib().ifctn_set_option(name.encode(), int(value)))
 
 
 def _dptr(arr: np.ndarray):

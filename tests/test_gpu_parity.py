@@ -84,6 +84,27 @@ def test_fp64_path_matches_oracle(dims, ranks):
     assert np.array_equal(r["Xg"][m], p.O.astype(np.float64)[m])
 
 
+@pytest.mark.parametrize("dims,ranks", SMALL, ids=["x".join(map(str, d)) for d, _ in SMALL])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_phased_factor_blocks_match_oracle(dims, ranks, precision):
+    """Every factor block forced into the phased form (partial Gram matrices
+    on many workgroups, then per-column solves)."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem(dims, ranks, seed=17)
+    prec = ifctn.IFCTN_FP64 if precision == "fp64" else ifctn.IFCTN_FP32
+    ifctn.set_option("phased_min", 0)
+    try:
+        r = run_both(p, 3, prec)
+    finally:
+        ifctn.set_option("phased_min", -1)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert relerr(r["Xg"], r["Xo"]) < tol
+    for key in r["Go"]:
+        assert relerr(r["Gg"][key], r["Go"][key]) < tol * 10, key
+    for gs, os_ in zip(r["gs"], r["os"]):
+        assert abs(gs["objective"] - os_["objective"]) <= tol * 10 * abs(os_["objective"])
+
+
 @pytest.mark.parametrize("dims,ranks", SMALL[:6], ids=["x".join(map(str, d)) for d, _ in SMALL[:6]])
 def test_fp32_path_matches_oracle(dims, ranks):
     from paper_2511_16358_amd import ifctn
