@@ -363,3 +363,68 @@ def served_problem(spec: ServedSpec, core: np.ndarray) -> Problem:
     return Problem(f"served{spec.index}", spec.dims, spec.ranks, O, mask.astype(np.uint8), X32, G0, 0.1,
                    SERVED["t_max"])
 
+
+# --------------------------------------------------------------------------
+# the paper's synthetic workload and rank grids (Sec. 5)
+# --------------------------------------------------------------------------
+def tucker_problem(seed: int = 0, missing: float = 0.8, dims=(20, 20, 20, 20), tucker=(5, 5, 5, 5),
+                   rank: int = 3) -> Problem:
+    """Order-4 20^4 tensor of Tucker rank (5,5,5,5) with core and factor
+    matrices drawn from U(0,1) (the synthetic experiment of Sec. 5), divided
+    by its largest entry, with a uniform random missing rate.  `rank` is the
+    iFCTN rank of every edge the solver uses; the rank grid below varies it."""
+    rng = np.random.default_rng(seed)
+    core = rng.uniform(0.0, 1.0, size=tucker)
+    X = core
+    for m, (I, r) in enumerate(zip(dims, tucker)):
+        U = rng.uniform(0.0, 1.0, size=(I, r))
+        X = np.moveaxis(np.tensordot(U, X, axes=([1], [m])), 0, m)   # mode-m product
+    X = X / np.max(np.abs(X))
+    mask = rng.random(dims) >= missing
+    X32 = X.astype(np.float32)
+    O = np.where(mask, X32, np.float32(0.0)).astype(np.float32)
+    obs = X32[mask].astype(np.float64)
+    rms = float(np.sqrt(np.mean(obs * obs))) if obs.size else 1.0
+    ranks = uniform_ranks(len(dims), rank)
+    G0 = initial_factors(rng, dims, ranks, rms)
+    return Problem("tucker20", tuple(dims), ranks, O, mask.astype(np.uint8), X32, G0, 0.1, 1000,
+                   {"missing": missing, "tucker": tucker})
+
+
+def rank_grid_uniform(N: int, values=(2, 3, 4, 5, 6, 7, 8)):
+    """One rank matrix per value, every edge equal."""
+    return [uniform_ranks(N, v) for v in values]
+
+
+def rank_grid_msi(r12=(2, 3, 6), r13=(3, 6)):
+    """The image rank grid of Sec. 5 for order-3 tensors: R_{1,2} over one set
+    and R_{1,3} = R_{2,3} over another (0-based modes: R[0][1], R[0][2] = R[1][2]).
+    The paper's sets reach 36; this library supports ranks up to 8, so the
+    default sets are the paper's values up to 8."""
+    out = []
+    for a in r12:
+        for b in r13:
+            r = np.zeros((3, 3), dtype=np.int64)
+            r[0][1] = r[1][0] = a
+            r[0][2] = r[2][0] = r[1][2] = r[2][1] = b
+            out.append(r)
+    return out
+
+
+def initial_factors_for(p: Problem, ranks, seed: int):
+    """Initial factors for another rank matrix on the same problem (same
+    scaling rule as the workloads)."""
+    obs = p.O[p.mask.astype(bool)].astype(np.float64)
+    rms = float(np.sqrt(np.mean(obs * obs))) if obs.size else 1.0
+    return initial_factors(np.random.default_rng(seed), p.dims, ranks, rms)
+
+
+def fibre_missing_mask(dims, ratio: float, fibre_mode: int, seed: int = 0):
+    """Fibre-missing sampling: whole mode-`fibre_mode` fibres are missing
+    (for an image-shaped H x W x B tensor and fibre_mode = 2, every band of a
+    missing pixel), chosen uniformly at a given ratio of the fibres."""
+    rng = np.random.default_rng(seed)
+    other = [d for m, d in enumerate(dims) if m != fibre_mode]
+    keep = rng.random(other) >= ratio
+    return np.repeat(np.expand_dims(keep, fibre_mode), dims[fibre_mode], axis=fibre_mode).astype(np.uint8)
+

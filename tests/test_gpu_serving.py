@@ -165,3 +165,30 @@ def test_destroy_with_queued_requests_returns():
     for q in range(5):
         srv.submit(p.O, p.mask, p.G0, p.dims, p.ranks, 30, tag=q)
     srv.close()      # drops the queued ones, waits for the resident one
+
+
+def test_rank_grid_batch_equals_alone():
+    """Rank selection as a served batch: one observed tensor and mask shared
+    by every rank matrix of the grid; each job's result is its result alone."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem((14, 12, 10), W.uniform_ranks(3, 2), seed=81, keep=0.5)
+    grid = W.rank_grid_msi()
+    O = torch.as_tensor(p.O).cuda()
+    M = torch.as_tensor(p.mask).cuda()
+    G0s = [W.initial_factors_for(p, r, seed=q) for q, r in enumerate(grid)]
+    srv = ifctn.Server(64 << 20, max_active=len(grid), num_streams=4, sweeps_per_round=4)
+    torch.cuda.synchronize()
+    for q, (r, G0) in enumerate(zip(grid, G0s)):
+        srv.submit(O, M, G0, p.dims, r, 40, eps=1e-4, tag=q)
+    got = {}
+    for _ in range(300):
+        for c in srv.poll(16, wait_ms=100):
+            got[c["tag"]] = c
+        if len(got) == len(grid):
+            break
+    srv.close()
+    assert len(got) == len(grid)
+    for q, (r, G0) in enumerate(zip(grid, G0s)):
+        X, st = ifctn.complete(p.O, p.mask, G0, p.dims, r, t_max=40, eps=1e-4)
+        assert np.array_equal(got[q]["X"].cpu().numpy(), X.cpu().numpy()), q
+        assert got[q]["stats"]["sweeps_done"] == st["sweeps_done"]

@@ -23,3 +23,24 @@ def test_recovery_planted30():
     assert err < 1e-3, err
     objs = [h["objective"] for h in hist]
     assert all(b <= a * (1 + 1e-12) + 1e-15 for a, b in zip(objs, objs[1:]))
+
+
+def test_tucker_workload_has_tucker_rank_5():
+    """The synthetic tensor of Sec. 5: every mode unfolding has rank 5."""
+    import numpy as np
+    from paper_2511_16358_amd import workloads as W
+    p = W.tucker_problem(seed=1, missing=0.8)
+    X = p.X_true.astype(np.float64)
+    assert X.shape == (20, 20, 20, 20) and abs(X.max() - 1.0) < 1e-6 and X.min() > 0
+    for m in range(4):
+        unf = np.moveaxis(X, m, 0).reshape(20, -1)
+        assert np.linalg.matrix_rank(unf, tol=1e-5 * np.linalg.norm(unf)) == 5
+    assert abs(1.0 - p.mask.mean() - 0.8) < 0.01
+
+
+def test_fibre_missing_mask():
+    import numpy as np
+    from paper_2511_16358_amd import workloads as W
+    m = W.fibre_missing_mask((40, 30, 7), 0.3, 2, seed=3)
+    assert np.all(m == m[:, :, :1])                 # whole fibres along the band mode
+    assert abs(1.0 - m[:, :, 0].mean() - 0.3) < 0.05
