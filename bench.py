@@ -303,7 +303,8 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the sweep of one job fits one GPU; see DESIGN.md for how it would shard)",
+              f"(one job's sweep runs on one GPU; the multi-GPU mode for these workloads is "
+              f"independent jobs per GPU)",
               file=sys.stderr)
         sys.exit(2)
     import torch
@@ -370,8 +371,13 @@ def main():
             "kernel": "k_contract (mode-k contraction, fused X step on mode 0)",
             "avg_us": round(per["contract"]["avg_us"], 2)}
 
-    Xf = job.x().cpu().numpy().astype(np.float64)
+    Xdev = job.x()
+    Xf = Xdev.cpu().numpy().astype(np.float64)
     rse = float(np.linalg.norm((Xf - p.X_true).ravel()) / np.linalg.norm(p.X_true.astype(np.float64).ravel()))
+    image = None
+    if len(p.dims) == 3 and args.workload == "msi256":
+        mp, ms, _, _ = ifctn.image_metrics(Xdev.float(), p.X_true)
+        image = {"mpsnr_db": round(mp, 3), "mssim": round(ms, 4)}
     job.close()
 
     cmp = None
@@ -416,6 +422,7 @@ def main():
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per.items()},
         "dominant_kernel_class": dominant,
         "rse_after_timed_sweeps": rse,
+        "image_metrics_after_timed_sweeps": image,
         "objective": st["objective"],
         "wall_s_timed": round(wall, 4),
     }

@@ -221,6 +221,21 @@ ifctn_status ifctn_server_queued(ifctn_server* server, int32_t* queued, int32_t*
  * release everything (NULL is accepted). */
 ifctn_status ifctn_server_destroy(ifctn_server* server);
 
+/* Image-quality metrics of Sec. 5 for an H x W x B tensor (row-major, bands
+ * the last mode) against a reference of the same shape, both on the device in
+ * float32 (precision = IFCTN_FP32) or float64 (IFCTN_FP64):
+ *   PSNR_b = 10 log10(peak^2 / MSE_b) over all pixels of band b (+inf when
+ *   the band is exact), MPSNR = mean over bands;
+ *   SSIM_b = mean over the positions where an 11 x 11 Gaussian window
+ *   (standard deviation 1.5, normalised) fits of
+ *   ((2 mu_x mu_y + C1)(2 s_xy + C2)) / ((mu_x^2 + mu_y^2 + C1)(s_x^2 + s_y^2 + C2)),
+ *   C1 = (0.01 peak)^2, C2 = (0.03 peak)^2 (Wang et al. 2004), MSSIM = mean over bands.
+ * psnr_host / ssim_host (nullable) receive the B per-band values.  H and W must
+ * be at least 11.  Allocates a small scratch buffer; synchronises the stream. */
+ifctn_status ifctn_image_metrics(const void* X_dev, const void* ref_dev, int64_t H, int64_t W, int64_t B,
+                                 int32_t precision, double peak, double* psnr_host, double* ssim_host,
+                                 double* mpsnr, double* mssim, void* stream);
+
 /* Process-wide tuning option, read when a job is created:
  *   "phased_min": a factor block uses the phased form (partial Gram matrices
  *   over ranges of the Gram weight set on many workgroups, then one

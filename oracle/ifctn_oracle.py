@@ -19,10 +19,11 @@ Decomposition for Tensor Completion", arXiv 2511.16358):
   D = diag(vec S_k), y_j and G_{i,k}.
 * eq. (updateX) -- the X step (:func:`update_x`).
 * Algorithm 1 -- initialisation, Gauss-Seidel order, stop rule (:func:`pam`).
-* Sec. 5 -- RSE and RMSE (:func:`rse`, :func:`rmse`).
+* Sec. 5 -- RSE and RMSE (:func:`rse`, :func:`rmse`), MPSNR and MSSIM of
+  image-shaped tensors (:func:`mpsnr`, :func:`mssim`; the standard
+  definitions the paper cites, Wang et al. 2004 for SSIM).
 
-Readings of the paper where it is silent or garbled (see the design doc for the
-list): the data term carries 1/2 (consistent with f and with eq. updateG);
+Readings of the paper where it is silent or garbled: the data term carries 1/2 (consistent with f and with eq. updateG);
 G_{k,m} is new for m < i and old for m > i inside block k, factors of modes
 < k are new; y_j is the product of the own-side edge matrices of mode k
 except the edge {k,i}; X^0 is O with zeros off Omega; RSE divides by the
@@ -183,6 +184,57 @@ def rmse(X_true, X, mask):
     miss = ~np.asarray(mask).astype(bool)
     d = (np.asarray(X_true, dtype=np.float64) - X)[miss]
     return float(np.sqrt(np.sum(d * d) / max(d.size, 1)))
+
+
+def gaussian_window(size=11, sigma=1.5):
+    """Normalised size x size Gaussian window of the SSIM definition."""
+    ax = np.arange(size, dtype=np.float64) - (size // 2)
+    g = np.exp(-(ax[:, None] ** 2 + ax[None, :] ** 2) / (2.0 * sigma * sigma))
+    return g / g.sum()
+
+
+def psnr_bands(X, ref, peak=1.0):
+    """PSNR of every band (last mode) of an H x W x B tensor: 10 log10(peak^2 / MSE)."""
+    X = np.asarray(X, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    out = []
+    for b in range(X.shape[2]):
+        mse = np.mean((X[:, :, b] - ref[:, :, b]) ** 2)
+        out.append(np.inf if mse == 0 else 10.0 * np.log10(peak * peak / mse))
+    return np.array(out)
+
+
+def ssim_band(x, y, peak=1.0, size=11, sigma=1.5):
+    """SSIM of two H x W images: the mean over every position where the
+    window fits of ((2 mu_x mu_y + C1)(2 s_xy + C2)) / ((mu_x^2 + mu_y^2 + C1)
+    (s_x^2 + s_y^2 + C2)), local statistics weighted by the Gaussian window,
+    C1 = (0.01 peak)^2, C2 = (0.03 peak)^2."""
+    x = np.asarray(x, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    g = gaussian_window(size, sigma)
+    c1, c2 = (0.01 * peak) ** 2, (0.03 * peak) ** 2
+    H, W = x.shape
+    vals = []
+    for h in range(H - size + 1):
+        for w in range(W - size + 1):
+            px = x[h:h + size, w:w + size]
+            py = y[h:h + size, w:w + size]
+            mx, my = np.sum(g * px), np.sum(g * py)
+            vx = np.sum(g * px * px) - mx * mx
+            vy = np.sum(g * py * py) - my * my
+            cxy = np.sum(g * px * py) - mx * my
+            vals.append(((2 * mx * my + c1) * (2 * cxy + c2)) / ((mx * mx + my * my + c1) * (vx + vy + c2)))
+    return float(np.mean(vals))
+
+
+def mpsnr(X, ref, peak=1.0):
+    """Mean over bands of the PSNR (Sec. 5)."""
+    return float(np.mean(psnr_bands(X, ref, peak)))
+
+
+def mssim(X, ref, peak=1.0):
+    """Mean over bands of the SSIM (Sec. 5)."""
+    return float(np.mean([ssim_band(X[:, :, b], ref[:, :, b], peak) for b in range(np.shape(X)[2])]))
 
 
 def num_parameters(dims, ranks):

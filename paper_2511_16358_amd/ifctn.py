@@ -33,7 +33,7 @@ EXPORTED = [
     "ifctn_reconstruct", "ifctn_get_factors", "ifctn_destroy", "ifctn_complete",
     "ifctn_assemble", "ifctn_timing_enable", "ifctn_timing_query", "ifctn_last_error",
     "ifctn_promote", "ifctn_server_create", "ifctn_server_submit", "ifctn_server_poll",
-    "ifctn_server_queued", "ifctn_server_destroy", "ifctn_set_option",
+    "ifctn_server_queued", "ifctn_server_destroy", "ifctn_set_option", "ifctn_image_metrics",
 ]
 
 
@@ -137,6 +137,8 @@ def lib():
         "ifctn_server_queued": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "ifctn_server_destroy": (st, [vp]),
         "ifctn_set_option": (st, [ctypes.c_char_p, ctypes.c_int64]),
+        "ifctn_image_metrics": (st, [vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, i32, ctypes.c_double,
+                                     dp, dp, dp, dp, vp]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -355,4 +357,23 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def image_metrics(X, ref, peak=1.0):
+    """MPSNR and MSSIM (ifctn_image_metrics) of an H x W x B tensor against a
+    reference; returns (mpsnr, mssim, psnr_per_band, ssim_per_band)."""
+    Xt = torch.as_tensor(X)
+    dt = torch.float64 if Xt.dtype == torch.float64 else torch.float32
+    Xt = Xt.to(device="cuda", dtype=dt).contiguous()
+    Rt = torch.as_tensor(ref).to(device="cuda", dtype=dt).contiguous()
+    if Xt.dim() != 3 or Xt.shape != Rt.shape:
+        raise ValueError("image_metrics needs two H x W x B tensors of the same shape")
+    H, Wd, B = (int(x) for x in Xt.shape)
+    ps = np.empty(B)
+    ss = np.empty(B)
+    mp, ms = ctypes.c_double(), ctypes.c_double()
+    _check(lib().ifctn_image_metrics(ctypes.c_void_p(Xt.data_ptr()), ctypes.c_void_p(Rt.data_ptr()), H, Wd, B,
+                                     IFCTN_FP64 if dt == torch.float64 else IFCTN_FP32, float(peak), _dptr(ps),
+                                     _dptr(ss), ctypes.byref(mp), ctypes.byref(ms), _stream_handle()))
+    return mp.value, ms.value, ps, ss
 

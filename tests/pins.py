@@ -485,7 +485,44 @@ def check_observed_rows(O):
     assert np.max(np.abs(np.array(rmses) / rms - 1.0)) < 0.01, rmses
 
 
+def check_image_metrics(O):
+    """MPSNR / MSSIM against closed forms and an independent route to the
+    local statistics (scipy's 2-D correlation with the same window)."""
+    from scipy.signal import correlate2d
+    rng = np.random.default_rng(4)
+    x = rng.uniform(0, 1, size=(17, 15))
+    assert abs(O.ssim_band(x, x) - 1.0) < 1e-12                     # identical images
+    y = np.clip(x + rng.normal(0, 0.1, size=x.shape), 0, 1)
+    assert abs(O.ssim_band(x, y) - O.ssim_band(y, x)) < 1e-14        # symmetric
+    # constant offset d: variances and covariance unchanged, so each window
+    # gives (2 mu (mu + d) + C1) / (mu^2 + (mu + d)^2 + C1)
+    d = 0.05
+    ax = np.arange(11) - 5.0
+    g = np.exp(-(ax[:, None] ** 2 + ax[None, :] ** 2) / (2 * 1.5 ** 2))
+    g /= g.sum()
+    mu = correlate2d(x, g, mode="valid")
+    c1 = 0.01 ** 2
+    want = np.mean((2 * mu * (mu + d) + c1) / (mu * mu + (mu + d) ** 2 + c1))
+    assert abs(O.ssim_band(x, x + d) - want) < 1e-12
+    # contrast change at equal means: a window with x -> mean + a (x - mean)
+    # has SSIM (2 a s^2 + C2) / ((1 + a^2) s^2 + C2); check on a flat-mean image
+    z = rng.uniform(0, 1, size=(11, 11))
+    gm = np.sum(g * z)
+    z2 = gm + 0.5 * (z - gm)
+    s2 = np.sum(g * z * z) - gm * gm
+    c2 = 0.03 ** 2
+    assert abs(O.ssim_band(z, z2) - (2 * 0.5 * s2 + c2) / ((1 + 0.25) * s2 + c2)) < 1e-12
+    # PSNR of a constant error d is 10 log10(1 / d^2); MPSNR / MSSIM are band means
+    X = rng.uniform(0, 1, size=(12, 13, 3))
+    assert np.allclose(O.psnr_bands(X + d, X), 10 * np.log10(1 / d ** 2), atol=1e-9)
+    assert np.allclose(O.psnr_bands(X + d, X, peak=2.0), 10 * np.log10(4 / d ** 2), atol=1e-9)
+    assert abs(O.mpsnr(X + d, X) - 10 * np.log10(1 / d ** 2)) < 1e-9
+    Y = np.clip(X + rng.normal(0, 0.05, size=X.shape), 0, 1)
+    assert abs(O.mssim(Y, X) - np.mean([O.ssim_band(Y[:, :, b], X[:, :, b]) for b in range(3)])) < 1e-15
+
+
 ALL_CHECKS = [
+    check_image_metrics,
     check_reconstruct_brute, check_n3_remark, check_cherry_kr, check_subnetwork,
     check_transposition, check_gauge, check_n2_ridge, check_block_probe, check_spd,
     check_x_update, check_sweep_replay, check_lemma2, check_stop_rule, check_fixed_point,

@@ -203,6 +203,42 @@ def _mut_cholesky_upper_misuse(m):
     return "update_factor", update_factor
 
 
+def _mut_ssim_c2_not_squared(m):
+    def ssim_band(x, y, peak=1.0, size=11, sigma=1.5):
+        x = np.asarray(x, dtype=np.float64)
+        y = np.asarray(y, dtype=np.float64)
+        g = m.gaussian_window(size, sigma)
+        c1, c2 = (0.01 * peak) ** 2, 0.03 * peak
+        H, W = x.shape
+        vals = []
+        for h in range(H - size + 1):
+            for w in range(W - size + 1):
+                px, py = x[h:h + size, w:w + size], y[h:h + size, w:w + size]
+                mx, my = np.sum(g * px), np.sum(g * py)
+                vx, vy = np.sum(g * px * px) - mx * mx, np.sum(g * py * py) - my * my
+                cxy = np.sum(g * px * py) - mx * my
+                vals.append(((2 * mx * my + c1) * (2 * cxy + c2)) / ((mx * mx + my * my + c1) * (vx + vy + c2)))
+        return float(np.mean(vals))
+    return "ssim_band", ssim_band
+
+
+def _mut_window_sigma(m):
+    def gaussian_window(size=11, sigma=1.5):
+        ax = np.arange(size, dtype=np.float64) - (size // 2)
+        g = np.exp(-(ax[:, None] ** 2 + ax[None, :] ** 2) / (sigma * sigma))   # lost the factor 2
+        return g / g.sum()
+    return "gaussian_window", gaussian_window
+
+
+def _mut_psnr_peak_not_squared(m):
+    def psnr_bands(X, ref, peak=1.0):
+        X = np.asarray(X, dtype=np.float64)
+        ref = np.asarray(ref, dtype=np.float64)
+        return np.array([10.0 * np.log10(peak / np.mean((X[:, :, b] - ref[:, :, b]) ** 2))
+                         for b in range(X.shape[2])])
+    return "psnr_bands", psnr_bands
+
+
 MUTATIONS = [
     _mut_reconstruct_drops_edge, _mut_edge_same_side, _mut_subnetwork_includes_k,
     _mut_y_includes_edge_ki, _mut_far_side_from_own, _mut_no_prox_in_b, _mut_no_prox_in_H,
@@ -210,6 +246,7 @@ MUTATIONS = [
     _mut_order_descending_i, _mut_jacobi_sweep, _mut_x_updated_before_factors,
     _mut_rel_uses_new_norm, _mut_rse_estimate_norm, _mut_rmse_all_entries,
     _mut_initial_x_keeps_unobserved, _mut_params_counts_edges_once, _mut_cholesky_upper_misuse,
+    _mut_ssim_c2_not_squared, _mut_window_sigma, _mut_psnr_peak_not_squared,
 ]
 
 
