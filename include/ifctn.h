@@ -243,6 +243,9 @@ ifctn_status ifctn_image_metrics(const void* X_dev, const void* ref_dev, int64_t
  *   holds at least this many entries; the one-workgroup-per-column form
  *   otherwise.  Both give the same solution of eq. (updateG) up to rounding.
  *   value < 0 restores the default (16384).
+ *   "contract_div", "contract_emin": a contraction workgroup covers about
+ *   max(contract_emin, nX / contract_div) tensor entries (defaults 1280 and
+ *   2048; values <= 0 restore them).
  * Unknown names: IFCTN_E_INVAL. */
 ifctn_status ifctn_set_option(const char* name, int64_t value);
 

@@ -156,6 +156,11 @@ struct ContractPlan {
 
 constexpr int kTargetBlocks = 1024;
 
+// tuning options (ifctn_set_option): < 0 = default
+std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1};
+long long contract_div() { long long v = g_contract_div.load(); return v > 0 ? v : 1280; }
+long long contract_emin() { long long v = g_contract_emin.load(); return v > 0 ? v : 2048; }
+
 constexpr size_t kMaxLds = 64 << 10;
 
 ContractPlan plan_contract(const Geo& g, int k) {
@@ -236,8 +241,9 @@ ContractPlan plan_contract(const Geo& g, int k) {
     a.plfast = (nc > 0 && a.cstride[nc - 1] < a.stride_k) ? 1 : 0;
     const long long jcapf = std::max<long long>(1, (long long)NT * 8 / a.Rprod);   // <= 8 slots per thread
     // workgroups of a few thousand elements: enough work to amortise the
-    // per-plane set-up, a few hundred workgroups over the chip
-    const long long E = std::min<long long>(65536, std::max<long long>(4096, g.nX / 320));
+    // per-plane set-up, several hundred workgroups over the chip (nX / 1280,
+    // at least 2048 entries: measured best on the 256 x 256 x 31 workload)
+    const long long E = std::min<long long>(65536, std::max<long long>(contract_emin(), g.nX / contract_div()));
     long long jn = (a.kind == 1 && a.plfast) ? std::min<long long>({(long long)a.Ik, jcapf, 8})
                                              : std::min<long long>(a.Ik, jcapf);
     long long JT = cdiv(a.Ik, jn);
@@ -340,6 +346,10 @@ ContractPlan plan_contract(const Geo& g, int k) {
 // and the partial buffers).  A plan that breaks one is rejected before any
 // kernel runs.
 bool plan_ok(const Geo& g, const ContractPlan& P, const char** why) {
+  if (P.a.nplanes >= (1LL << 31)) {
+    *why = "more than 2^31 planes";
+    return false;
+  }
   const ContractArgs& a = P.a;
   if ((long long)a.JT * a.jn < a.Ik || (long long)(a.JT - 1) * a.jn >= a.Ik) { *why = "j tiling"; return false; }
   if ((long long)a.S * a.PPW < a.nplanes || (long long)(a.S - 1) * a.PPW >= a.nplanes) { *why = "plane split"; return false; }
@@ -1127,6 +1137,14 @@ ifctn_status ifctn_set_option(const char* name, int64_t value) {
   if (!name) return fail(IFCTN_E_INVAL, "name is NULL");
   if (std::strcmp(name, "phased_min") == 0) {
     g_phased_min.store(value < 0 ? -1 : (long long)value);
+    return IFCTN_OK;
+  }
+  if (std::strcmp(name, "contract_div") == 0) {
+    g_contract_div.store(value);
+    return IFCTN_OK;
+  }
+  if (std::strcmp(name, "contract_emin") == 0) {
+    g_contract_emin.store(value);
     return IFCTN_OK;
   }
   return fail(IFCTN_E_INVAL, "unknown option '%s'", name);

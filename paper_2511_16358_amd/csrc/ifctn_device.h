@@ -34,6 +34,30 @@ __device__ __forceinline__ long long eaddr(const EdgeRef e, long long a, long lo
   return e.off + a * e.s1 + b * e.s2;
 }
 
+// Division by a loop-invariant divisor through a float reciprocal: for
+// 0 <= n < 2^22 the estimate trunc(n * (1/d)) is within one of n / d (the two
+// roundings are below 2^-23 relative), and one correction step makes it exact.
+struct FDiv {
+  int d;
+  float r;
+};
+
+__device__ __forceinline__ FDiv mkdiv(int d) { return FDiv{d, 1.0f / (float)d}; }
+
+__device__ __forceinline__ int fdiv(int n, const FDiv f) {
+  int q = (int)((float)n * f.r);
+  const int rem = n - q * f.d;
+  q += (rem >= f.d ? 1 : 0) - (rem < 0 ? 1 : 0);
+  return q;
+}
+
+// quotient and remainder; n may exceed the fast range (rare: falls back)
+__device__ __forceinline__ int fdivmod(int n, const FDiv f, int* rem) {
+  const int q = n < (1 << 22) ? fdiv(n, f) : n / f.d;
+  *rem = n - q * f.d;
+  return q;
+}
+
 // for (e = tid; e < n; e += NT) use(e, load(e)), with the loads of U
 // consecutive iterations issued before any of them is consumed (the index is
 // clamped so that every load is in bounds and the body has no branches)
@@ -428,13 +452,17 @@ __device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0
                                             TC* t0, bool con, bool upd) {
   const TC* __restrict__ Wc = (const TC*)a.Wc;
   const int tid = threadIdx.x, If = a.If, Rc = a.Rc, jn = a.jn;
+  FDiv fcd[NC > 0 ? NC : 1];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) fcd[c] = mkdiv(a.cdim[c]);
+  const FDiv fIf = mkdiv(If);
   for (int e = tid; e < np; e += NT) {
-    long long p = pb0 + e, base = 0;
+    long long base = 0;
+    int p = (int)(pb0 + e);          // plane index (< 2^31: the plane count is checked on the host)
     int ic[MAXC > 0 ? MAXC : 1];
 #pragma unroll
     for (int c = NC - 1; c >= 0; --c) {
-      ic[c] = (int)(p % a.cdim[c]);
-      p /= a.cdim[c];
+      p = fdivmod(p, fcd[c], &ic[c]);
       base += (long long)ic[c] * a.cstride[c];
     }
     TC sv = (TC)1;
@@ -451,7 +479,8 @@ __device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0
   for_batched<4>(
       np * If,
       [&](int e) {
-        const int pl = e / If, ff = e - pl * If;
+        int ff;
+        const int pl = fdivmod(e, fIf, &ff);
         TC v = sccl[pl];
 #pragma unroll
         for (int c = 0; c < NC; ++c) v *= Wc[eaddr(a.ecf[c], pidx[pl * MAXC + c], ff)];
@@ -462,13 +491,13 @@ __device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0
     for_batched<4>(
         np * Rc,
         [&](int e) {
-          const int pl = e / Rc;
-          int rr = e - pl * Rc;
+          int rr;
+          const int pl = fdivmod(e, mkdiv(Rc), &rr);
           double v = 1.0;
 #pragma unroll
           for (int c = NC - 1; c >= 0; --c) {
-            const int r = rr % a.crank[c];
-            rr /= a.crank[c];
+            int r;
+            rr = fdivmod(rr, mkdiv(a.crank[c]), &r);
             v *= a.G[a.gcoff[c] + (long long)r * a.cdim[c] + pidx[pl * MAXC + c]];
           }
           return v;
@@ -479,15 +508,17 @@ __device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0
     for_batched<4>(
         np * jcnt,
         [&](int e) {
-          const int pl = e / jcnt, jl = e - pl * jcnt;
+          int jl;
+          const int pl = fdivmod(e, mkdiv(jcnt), &jl);
           TC v = (TC)1;
 #pragma unroll
           for (int c = 0; c < NC; ++c) v *= Wc[eaddr(a.e0c[c], j0 + jl, pidx[pl * MAXC + c])];
           return v;
         },
         [&](int e, TC v) {
-          const int pl = e / jcnt;
-          t0[pl * jn + (e - pl * jcnt)] = v;
+          int jl;
+          const int pl = fdivmod(e, mkdiv(jcnt), &jl);
+          t0[pl * jn + jl] = v;
         });
   }
   __syncthreads();
@@ -510,21 +541,42 @@ template <int SPT>
 struct Slots {
   double acc[SPT];
   int aoff[SPT], toff[SPT];
+  int jls[SPT], cols[SPT];     // row of U and canonical U column of each slot
   int psub;
-  __device__ __forceinline__ void init(int jcnt, int Rprod, int Rf, int psplit) {
-    const int tid = threadIdx.x;
-    psub = tid % psplit;            // NT is a multiple of psplit: the same for every slot
+  template <int NC>
+  __device__ __forceinline__ void init(const ContractArgs& a, int jcnt) {
+    const int tid = threadIdx.x, Rprod = a.Rprod, Rf = a.Rf, psplit = a.psplit;
+    const int lgp = __ffs(psplit) - 1;   // psplit is a power of two
+    psub = tid & (psplit - 1);           // NT is a multiple of psplit: the same for every slot
+    const FDiv fR = mkdiv(Rprod), fRf = mkdiv(Rf);
+    FDiv fcr[NC > 0 ? NC : 1];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) fcr[c] = mkdiv(a.crank[c]);
 #pragma unroll
     for (int q = 0; q < SPT; ++q) {
       acc[q] = 0.0;
       aoff[q] = -1;
       toff[q] = 0;
+      jls[q] = 0;
+      cols[q] = 0;
       const int s = q * NT + tid;
       if (s < jcnt * Rprod * psplit) {
-        const int b = s / psplit;
-        const int jl = b / Rprod, sl = b - jl * Rprod;
-        aoff[q] = sl / Rf;
-        toff[q] = jl * Rf + (sl - (sl / Rf) * Rf);
+        const int b = s >> lgp;
+        int sl, rf;
+        const int jl = fdivmod(b, fR, &sl);
+        const int rc = fdivmod(sl, fRf, &rf);
+        aoff[q] = rc;
+        toff[q] = jl * Rf + rf;
+        jls[q] = jl;
+        long long col = (long long)rf * a.ustf;
+        int rr = rc;
+#pragma unroll
+        for (int c = NC - 1; c >= 0; --c) {
+          int r;
+          rr = fdivmod(rr, fcr[c], &r);
+          col += (long long)r * a.ustc[c];
+        }
+        cols[q] = (int)col;
       }
     }
   }
@@ -553,7 +605,7 @@ struct Slots {
   // canonical U column (modes != k ascending, row-major)
   template <int NC>
   __device__ __forceinline__ void write(const ContractArgs& a, double* comb, int sp, int j0) {
-    const int tid = threadIdx.x, psplit = a.psplit, Rprod = a.Rprod, Rf = a.Rf;
+    const int tid = threadIdx.x, psplit = a.psplit, Rprod = a.Rprod;
     if (psplit > 1) {
 #pragma unroll
       for (int q = 0; q < SPT; ++q)
@@ -566,17 +618,7 @@ struct Slots {
         const int s = q * NT + tid;
         double v = acc[q];
         for (int t = 1; t < psplit; ++t) v += comb[s + t];
-        const int b = s / psplit;
-        const int jl = b / Rprod, sl = b - jl * Rprod;
-        int rc = sl / Rf;
-        long long col = (long long)(sl - rc * Rf) * a.ustf;
-#pragma unroll
-        for (int c = NC - 1; c >= 0; --c) {
-          const int r = rc % a.crank[c];
-          rc /= a.crank[c];
-          col += (long long)r * a.ustc[c];
-        }
-        a.Upart[((long long)sp * a.Ik + j0 + jl) * Rprod + col] = v;
+        a.Upart[((long long)sp * a.Ik + j0 + jls[q]) * Rprod + cols[q]] = v;
       }
     }
   }
@@ -626,14 +668,15 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
 
   Slots<SPT> sl;
   if (CON) {
-    sl.init(jcnt, a.Rprod, Rf, a.psplit);
+    sl.template init<NC>(a, jcnt);
     load_gf<TC>(a, gf);
   }
   if (UPD)
     for_batched<4>(
         jcnt * If,
         [&](int e) {
-          const int jl = e / If, ff = e - jl * If;
+          int ff;
+          const int jl = fdivmod(e, mkdiv(If), &ff);
           return Wc[eaddr(a.e0f, j0 + jl, ff)];
         },
         [&](int e, TC v) { w0f[e] = v; });
@@ -646,6 +689,7 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
     plane_setup<TC, NC>(a, pb0, np, jcnt, j0, pbase, pidx, sccl, scf, acoef, t0, CON, UPD);
     const int rows = np * jcnt;
     const int passes = (rows + rpp - 1) / rpp;
+    const FDiv frow = mkdiv(a.plfast ? np : jcnt);
     for (int ps = 0; ps < passes; ++ps) {
       const int row = ps * rpp + tid / fch;
       TC t[MAXR];
@@ -653,8 +697,10 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
       for (int r = 0; r < MAXR; ++r) t[r] = (TC)0;
       const bool rok = row < rows;
       const int rowc = rok ? row : rows - 1;
-      const int pl = a.plfast ? rowc % np : rowc / jcnt;
-      const int jl = a.plfast ? rowc / np : rowc % jcnt;
+      int rq;
+      const int rd = fdivmod(rowc, frow, &rq);
+      const int pl = a.plfast ? rq : rd;
+      const int jl = a.plfast ? rd : rq;
       const long long base = pbase[pl] + (long long)(j0 + jl) * a.stride_k;
       const TC* sr = scf + pl * If;
       const TC* wr = w0f + jl * If;
@@ -744,7 +790,7 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
   const long long sf = a.stride_f;
 
   Slots<SPT> sl;
-  sl.init(jcnt, a.Rprod, Rf, a.psplit);
+  sl.template init<NC>(a, jcnt);
   load_gf<TC>(a, gf);
 
   for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
@@ -755,14 +801,15 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
     const int fchunk = (fhi - flo + fg - 1) / fg;
     const int npass = fg > 1 ? 1 : (NI + NT - 1) / NT;
     for (int ps = 0; ps < npass; ++ps) {
-      const int g = fg > 1 ? tid / NI : 0;
+      const int g = fg > 1 ? fdiv(tid, mkdiv(NI)) : 0;
       const int it = fg > 1 ? tid - g * NI : ps * NT + tid;
       const bool ok = g < fg && it < NI;
       const int itc = ok ? it : NI - 1;
       TC t[MAXR];
 #pragma unroll
       for (int r = 0; r < MAXR; ++r) t[r] = (TC)0;
-      const int pl = itc / jcnt, jl = itc - pl * jcnt;
+      int jl;
+      const int pl = fdivmod(itc, mkdiv(jcnt), &jl);
       const TC* sr = scf + pl * If;
       const long long base = pbase[pl] + j0 + jl;
       const int lo = flo + (ok ? g : 0) * fchunk, hi = ok ? min(fhi, lo + fchunk) : lo;
@@ -789,8 +836,9 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
         for (int e = tid; e < NI * Rf; e += NT) {
           TC v = (TC)0;
           for (int q = 0; q < fg; ++q) v += tpart[q * NI * Rf + e];
-          const int i2 = e / Rf, r = e - i2 * Rf;
-          const int p2 = i2 / jcnt, j2 = i2 - p2 * jcnt;
+          int r, j2;
+          const int i2 = fdivmod(e, mkdiv(Rf), &r);
+          const int p2 = fdivmod(i2, mkdiv(jcnt), &j2);
           Tl[(p2 * jn + j2) * Rf + r] = v;
         }
       } else if (ok) {
