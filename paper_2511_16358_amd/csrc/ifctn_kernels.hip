@@ -213,7 +213,11 @@ __device__ __forceinline__ double ldlt_solve(const double* Hs, const double* bs,
 #pragma unroll
     for (int q = 0; q < c; ++q) dc -= L[c][q] * L[c][q] * d[q];
     d[c] = dc;
-    inv[c] = 1.0 / dc;
+    // reciprocal: hardware estimate refined by two Newton steps (dc >= rho > 0)
+    double rc = __builtin_amdgcn_rcp(dc);
+    rc = fma(rc, fma(-dc, rc, 1.0), rc);
+    rc = fma(rc, fma(-dc, rc, 1.0), rc);
+    inv[c] = rc;
 #pragma unroll
     for (int r = c + 1; r < R; ++r) {
       double v = A[r][c];
@@ -360,7 +364,9 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
     // weights w_j(d) = prod_{m in d} W_{k,m}(j, i_m)^2 are formed once in LDS;
     // the first Q entries of the tile are requested before that, so the two
     // latencies overlap.
-    const int cpp = NT / np;
+    // groups of d per Gram entry: enough d per thread to keep loads in flight,
+    // few enough partials for the serial reduction below
+    const int cpp = (int)min((long long)(NT / np), max(1LL, (B.D + 3) / 4));
     const int p_me = tid % np, c_me = tid / np;
     double hacc = 0.0;
     for (long long d0 = 0; d0 < B.D; d0 += TD) {
@@ -400,9 +406,9 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       }
       if (d0 + TD < B.D) __syncthreads();
     }
-    const int cpr = NT / R;
-    const int r_me = tid % R, cb = tid / R;
     const int nother = a.Rprod / R;
+    const int cpr = min(NT / R, nother);    // as many column groups as there are terms
+    const int r_me = tid % R, cb = tid / R;
     double bacc = 0.0;
     if (cb < cpr) {
       for (int o = cb; o < nother; o += cpr) {
@@ -584,7 +590,7 @@ __global__ __launch_bounds__(NT) void k_solve_col(PhaseArgs a) {
     for (int r = 0; r < MAXR; ++r) gpre[r] = r < R ? Gik[(long long)r * B.Ii + y] : 0.0;
   }
   // H_j: thread (p, c) sums the ranges ks = c mod cpp in ascending order
-  const int cpp = NT / np;
+  const int cpp = min(NT / np, max(1, a.KS));
   const int p_me = tid % np, c_me = tid / np;
   double hacc = 0.0;
   if (c_me < cpp) {
@@ -601,9 +607,9 @@ __global__ __launch_bounds__(NT) void k_solve_col(PhaseArgs a) {
     for (; q < a.KS; q += cpp) hacc += hp[(long long)q * stride];
   }
   __syncthreads();                       // gk complete
-  const int cpr = NT / R;
-  const int r_me = tid % R, cb = tid / R;
   const int nother = a.Rprod / R;
+  const int cpr = min(NT / R, nother);
+  const int r_me = tid % R, cb = tid / R;
   double bacc = 0.0;
   if (cb < cpr) {
     const double* u = a.Ufin + (long long)j * a.Rprod;
