@@ -271,9 +271,29 @@ ContractPlan plan_contract(const Geo& g, int k) {
       while (fch < 64 && a.If / (2 * fch) >= 4) fch *= 2;
       a.fch = fch;
     }
+    // two or more c-modes: contract the last one first (staged accumulation)
+    // when the batches and workgroups can hold whole groups of its planes
+    a.stage = 0;
+    if (nc >= 2 && a.crank[nc - 1] >= 2) {
+      const int cdl = a.cdim[nc - 1];
+      const int pbmax = a.kind == 1 ? 64 : 32;
+      if (cdl <= pbmax) {
+        a.PPW = cdiv(a.PPW, cdl) * cdl;
+        a.S = (int)cdiv(a.nplanes, a.PPW);
+        a.stage = 1;
+        a.cdl = cdl;
+        a.Rl = a.crank[nc - 1];
+        a.Rc2 = a.Rc / a.Rl;
+        a.gloff = a.gcoff[nc - 1];
+        a.PB = (int)std::max<long long>(cdl, (std::min<long long>(a.PPW, pbmax) / cdl) * cdl);
+        while (a.PB > cdl && contract_smem_bytes(g.dtype, a) > kMaxLds) a.PB -= cdl;
+        if (contract_smem_bytes(g.dtype, a) > kMaxLds) a.stage = 0;   // plain accumulation
+      }
+    }
     while (a.PB > 1 && contract_smem_bytes(g.dtype, a) > kMaxLds) a.PB = std::max(1, a.PB * 3 / 4);
     int ps = 1;
-    while (ps < 16 && jn * a.Rprod * ps * 2 <= NT && a.PB >= 2 * ps) ps *= 2;
+    const int units = a.stage ? a.PB / a.cdl : a.PB;   // what the split threads share: planes or groups
+    while (ps < 16 && jn * a.Rprod * ps * 2 <= NT && units >= 2 * ps) ps *= 2;
     a.psplit = ps;
     const long long slots = jn * a.Rprod * a.psplit;
     int spt = 1;
@@ -346,6 +366,11 @@ ContractPlan plan_contract(const Geo& g, int k) {
 // and the partial buffers).  A plan that breaks one is rejected before any
 // kernel runs.
 bool plan_ok(const Geo& g, const ContractPlan& P, const char** why) {
+  if (P.a.stage && (P.a.cdl < 1 || P.a.PB % P.a.cdl || P.a.PPW % P.a.cdl || P.a.nplanes % P.a.cdl ||
+                    P.a.Rl * P.a.Rc2 != P.a.Rc || P.a.kind == 0)) {
+    *why = "staged accumulation groups";
+    return false;
+  }
   if (P.a.nplanes >= (1LL << 31)) {
     *why = "more than 2^31 planes";
     return false;
@@ -510,10 +535,10 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
       const ContractArgs& a = P.a;
       std::fprintf(stderr,
                    "[ifctn plan] k=%d f=%d kind=%d plfast=%d ord=%d%d%d Ik=%d If=%d LDF=%d nc=%d Rf=%d Rc=%d Rprod=%d jn=%d JT=%d S=%d "
-                   "PPW=%lld PB=%d FS=%d nplanes=%lld spt=%d fch=%d psplit=%d smem=%zu blocks=%lld upart=%lld | Q blocks=%lld size=%lld\n",
+                   "PPW=%lld PB=%d FS=%d nplanes=%lld spt=%d fch=%d psplit=%d smem=%zu blocks=%lld upart=%lld stage=%d cdl=%d Rl=%d | Q blocks=%lld size=%lld\n",
                    k, a.f, a.kind, a.plfast, a.ord[0], a.ord[1], a.ord[2], a.Ik, a.If, a.LDF, a.nc, a.Rf, a.Rc, a.Rprod, a.jn, a.JT, a.S, a.PPW, a.PB,
                    a.FS, a.nplanes, P.spt, a.fch, a.psplit, P.smem, (long long)a.JT * a.S * a.FS,
-                   (long long)a.S * a.FS * a.Ik * a.Rprod,
+                   (long long)a.S * a.FS * a.Ik * a.Rprod, a.stage, a.cdl, a.Rl,
                    Q.blk0[Q.ni], qs);
     }
     if (cp) cp[k] = P;

@@ -423,7 +423,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
 // accumulation into float64 slots and the split partials of U_k.
 // --------------------------------------------------------------------------
 struct FLayout {
-  size_t pbase, pidx, acoef, scc, scf, t0, w0f, gf, T, tpart, red, total;
+  size_t pbase, pidx, acoef, scc, scf, t0, w0f, gf, T, tpart, red, T2, gl, total;
 };
 
 __host__ __device__ inline FLayout flayout(int tcsz, const ContractArgs& a) {
@@ -440,6 +440,9 @@ __host__ __device__ inline FLayout flayout(int tcsz, const ContractArgs& a) {
   L.T = o;     o = al16(o + std::max((size_t)a.PB * a.jn * a.Rf * tcsz, (size_t)NT * 8));
   L.tpart = o; o = al16(o + (a.kind == 2 ? (size_t)NT * a.Rf * tcsz : 0));
   L.red = o;   o = al16(o + 4 * 3 * 8);
+  // staged accumulation: partial contraction over the last c-mode, its factor
+  L.T2 = o;    o = al16(o + (a.stage ? (size_t)(a.PB / a.cdl) * a.jn * a.Rl * a.Rf * 8 : 0));
+  L.gl = o;    o = al16(o + (a.stage ? (size_t)a.cdl * MAXR * 8 : 0));
   L.total = o;
   return L;
 }
@@ -487,7 +490,26 @@ __device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0
         return v;
       },
       [&](int e, TC v) { scf[e] = v; });
-  if (con) {
+  if (con && a.stage) {
+    // per group of cdl planes: product over the c-modes but the last
+    const int ng = np / a.cdl, Rc2 = a.Rc2;
+    for_batched<4>(
+        ng * Rc2,
+        [&](int e) {
+          int rr;
+          const int g = fdivmod(e, mkdiv(Rc2), &rr);
+          const int pl = g * a.cdl;
+          double v = 1.0;
+#pragma unroll
+          for (int c = NC - 2; c >= 0; --c) {
+            int r;
+            rr = fdivmod(rr, mkdiv(a.crank[c]), &r);
+            v *= a.G[a.gcoff[c] + (long long)r * a.cdim[c] + pidx[pl * MAXC + c]];
+          }
+          return v;
+        },
+        [&](int e, double v) { acoef[e] = v; });
+  } else if (con) {
     for_batched<4>(
         np * Rc,
         [&](int e) {
@@ -565,8 +587,16 @@ struct Slots {
         int sl, rf;
         const int jl = fdivmod(b, fR, &sl);
         const int rc = fdivmod(sl, fRf, &rf);
-        aoff[q] = rc;
-        toff[q] = jl * Rf + rf;
+        if (a.stage) {
+          // rc = rc2 * Rl + rl (the last c-mode is the fastest digit)
+          int rl;
+          const int rc2 = fdivmod(rc, mkdiv(a.Rl), &rl);
+          aoff[q] = rc2;
+          toff[q] = (jl * a.Rl + rl) * Rf + rf;
+        } else {
+          aoff[q] = rc;
+          toff[q] = jl * Rf + rf;
+        }
         jls[q] = jl;
         long long col = (long long)rf * a.ustf;
         int rr = rc;
@@ -624,6 +654,42 @@ struct Slots {
   }
 };
 
+// Staged accumulation of a batch: T2(g, j, r_l, r_f) = sum over the last
+// c-mode index i of G_{m_last,k}(r_l, i) T(g cdl + i, j, r_f) in float64, then
+// the slots accumulate over the groups g.
+template <int SPT, typename TC>
+__device__ __forceinline__ void staged_accumulate(const ContractArgs& a, Slots<SPT>& sl, const double* acoef,
+                                                  const TC* Tl, double* T2, const double* gl, int np, int jcnt) {
+  const int tid = threadIdx.x, jn = a.jn, Rf = a.Rf, Rl = a.Rl, cdl = a.cdl;
+  const int ng = np / cdl;
+  const int per = jcnt * Rl * Rf;
+  const FDiv fper = mkdiv(per), fRf = mkdiv(Rf), fRl = mkdiv(Rl);
+  for (int e = tid; e < ng * per; e += NT) {
+    int rem, rf, rl;
+    const int g = fdivmod(e, fper, &rem);
+    const int t = fdivmod(rem, fRf, &rf);
+    const int jl = fdivmod(t, fRl, &rl);
+    const TC* tp = Tl + ((long long)g * cdl * jn + jl) * Rf + rf;
+    double v = 0.0;
+    for (int i = 0; i < cdl; ++i) v += gl[i * MAXR + rl] * (double)tp[(long long)i * jn * Rf];
+    T2[((g * jn + jl) * Rl + rl) * Rf + rf] = v;
+  }
+  __syncthreads();
+  sl.accumulate(acoef, (const double*)T2, ng, jn, a.Rc2, Rl * Rf, a.psplit);
+}
+
+// G_{m_last,k} as gl[i][r] (float64, zero-padded to MAXR ranks)
+__device__ __forceinline__ void load_gl(const ContractArgs& a, double* gl) {
+  const int cdl = a.cdl, Rl = a.Rl;
+  for_batched<4>(
+      cdl * MAXR,
+      [&](int e) {
+        const int i = e / MAXR, r = e - i * MAXR;
+        return r < Rl ? a.G[a.gloff + (long long)r * cdl + i] : 0.0;
+      },
+      [&](int e, double v) { gl[e] = v; });
+}
+
 __device__ __forceinline__ void block_norms(double dx2, double x2, double f2, double* red, double* out) {
   const int tid = threadIdx.x;
   const double v0 = wave_sum(dx2), v1 = wave_sum(x2), v2 = wave_sum(f2);
@@ -667,9 +733,12 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
   const int If = a.If, Rf = a.Rf, jn = a.jn;
 
   Slots<SPT> sl;
+  double* T2 = (double*)(smem + Ly.T2);
+  double* gl = (double*)(smem + Ly.gl);
   if (CON) {
     sl.template init<NC>(a, jcnt);
     load_gf<TC>(a, gf);
+    if (NC >= 2 && a.stage) load_gl(a, gl);
   }
   if (UPD)
     for_batched<4>(
@@ -756,7 +825,12 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
       }
     }
     __syncthreads();
-    if (CON) sl.accumulate(acoef, Tl, np, jn, a.Rc, Rf, a.psplit);
+    if (CON) {
+      if (NC >= 2 && a.stage)
+        staged_accumulate(a, sl, acoef, Tl, T2, gl, np, jcnt);
+      else
+        sl.accumulate(acoef, Tl, np, jn, a.Rc, Rf, a.psplit);
+    }
     __syncthreads();
   }
   if (CON) sl.template write<NC>(a, (double*)(smem + Ly.T), sp, j0);
@@ -790,8 +864,11 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
   const long long sf = a.stride_f;
 
   Slots<SPT> sl;
+  double* T2 = (double*)(smem + Ly.T2);
+  double* gl = (double*)(smem + Ly.gl);
   sl.template init<NC>(a, jcnt);
   load_gf<TC>(a, gf);
+  if (NC >= 2 && a.stage) load_gl(a, gl);
 
   for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
     const int np = (int)min((long long)a.PB, p_end - pb0);
@@ -848,7 +925,10 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
       }
     }
     __syncthreads();
-    sl.accumulate(acoef, Tl, np, jn, a.Rc, Rf, a.psplit);
+    if (NC >= 2 && a.stage)
+      staged_accumulate(a, sl, acoef, Tl, T2, gl, np, jcnt);
+    else
+      sl.accumulate(acoef, Tl, np, jn, a.Rc, Rf, a.psplit);
     __syncthreads();
   }
   sl.template write<NC>(a, (double*)(smem + Ly.T), spf, j0);

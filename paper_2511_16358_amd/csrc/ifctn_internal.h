@@ -97,6 +97,12 @@ struct ContractArgs {
   int plfast;            // rows: consecutive planes are closer in memory than consecutive j
   int FS;                // columns: fibre range split over FS workgroups (partials S * FS)
   long long PPW, nplanes;
+  // staged accumulation (two or more c-modes): the planes of a batch come in
+  // whole groups of the last c-mode (size cdl, rank Rl); that mode is
+  // contracted first, U then accumulates over the groups with the product of
+  // the other c-modes' factors (Rc2 = Rc / Rl terms) instead of over planes
+  int stage, cdl, Rl, Rc2;
+  long long gloff;       // offset of G_{m_last,k} (Rl x cdl)
   // fused X step (k == 0 only)
   EdgeRef e0c[MAXC];     // W(i_0, i_m) for the c-modes
   EdgeRef e0f;           // W(i_0, i_f)

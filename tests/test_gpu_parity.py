@@ -63,6 +63,7 @@ SMALL = [
     ((33, 17, 40), W.uniform_ranks(3, 5)),      # several tiles and ragged tails
     ((3, 1, 4), W.uniform_ranks(3, 2)),          # a mode of size 1
     ((12, 20, 3, 9), np.array([[0, 2, 3, 1], [2, 0, 2, 3], [3, 2, 0, 2], [1, 3, 2, 0]])),
+    ((8, 7, 9, 6, 10), W.uniform_ranks(5, 3)),   # order 5: staged accumulation over two c-modes
 ]
 
 
