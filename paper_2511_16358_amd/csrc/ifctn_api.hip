@@ -425,7 +425,7 @@ QArgs plan_q(const Geo& g, int k, long long* qsize) {
         ++q;
       }
     it.D = D;
-    int lanes = (int)std::min<long long>(64, cdiv(it.Ii, 8));
+    int lanes = (int)std::min<long long>(64, cdiv(it.Ii, 4));   // about 4 fibre entries per lane
     int lg = 0;
     while ((1 << lg) < lanes) ++lg;
     it.lg2P = lg;

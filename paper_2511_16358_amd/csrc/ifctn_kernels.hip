@@ -121,7 +121,7 @@ __device__ __forceinline__ void gram_work(const double* __restrict__ W64, const 
     }
     const int lo = ch * it.CH, hi = min(Ii, lo + it.CH);
     const double* Gik = Gp + it.gik;
-    constexpr int XU = R <= 4 ? 4 : 2;
+    constexpr int XU = R <= 6 ? 4 : 2;
     for (int x0 = lo; x0 < hi; x0 += XU) {
       double wv[XU][MAXC], g[XU][R];
 #pragma unroll
