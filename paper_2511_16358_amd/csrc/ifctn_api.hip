@@ -157,7 +157,8 @@ struct ContractPlan {
 constexpr int kTargetBlocks = 1024;
 
 // tuning options (ifctn_set_option): < 0 = default
-std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1};
+std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1};
+bool merge_gram() { return g_merge_gram.load() != 0; }
 long long contract_div() { long long v = g_contract_div.load(); return v > 0 ? v : 1280; }
 long long contract_emin() { long long v = g_contract_emin.load(); return v > 0 ? v : 2048; }
 
@@ -472,6 +473,7 @@ struct ifctn_job {
   QArgs qplan[MAXN];
   SolveArgs splan[MAXN];
   bool phased[MAXN] = {};
+  bool merge[MAXN] = {};       // Gram weights inside the contraction launch
   PhaseArgs pplan[MAXN][MAXN - 1];
   int nnorm = 0, ndg = 0;
   bool pending = false;
@@ -699,10 +701,31 @@ struct ContractCall {
   bool upd, con;
 };
 
+// The Gram weights of block k ride along as extra workgroups of the
+// contraction launch (same inputs, no ordering between them), for the
+// layout-specialised contraction kernels.
+bool gram_merged(const ifctn_job* J, int k) {
+  return J->cplan[k].a.kind != 0 && J->qplan[k].blk0[J->qplan[k].ni] > 0 && J->merge[k];
+}
+
 hipError_t do_contract(ifctn_job* J, const void* c) {
   const ContractCall* cc = (const ContractCall*)c;
   const ContractPlan& P = J->cplan[cc->k];
   const int kt = J->bf16_phase ? KT_BF16 : (J->g.dtype ? KT_F64 : KT_F32);
+  if (cc->con && gram_merged(J, cc->k)) {
+    ContractArgs a = P.a;
+    const QArgs& q = J->qplan[cc->k];
+    a.gblocks = (int)q.blk0[q.ni];
+    a.gr.dit = q.dit;
+    a.gr.ni = q.ni;
+    a.gr.nd = q.nd;
+    a.gr.ndd = q.ndd;
+    for (int t = 0; t < MAXN; ++t) a.gr.blk0[t] = q.blk0[t];
+    a.gr.W64 = q.W64;
+    a.gr.G = q.G;
+    a.gr.Q = q.Q;
+    return launch_contract(kt, cc->upd, cc->con, P.spt, a, P.smem, J->stream);
+  }
   return launch_contract(kt, cc->upd, cc->con, cc->con ? P.spt : 1, P.a, P.smem, J->stream);
 }
 
@@ -724,8 +747,10 @@ hipError_t run_sweep(ifctn_job* J) {
   const int N = J->g.N;
   hipError_t e;
   for (int k = 0; k < N; ++k) {
-    e = timed(J, KC_GRAM, do_gram, &J->qplan[k]);
-    if (e != hipSuccess) return e;
+    if (!gram_merged(J, k)) {
+      e = timed(J, KC_GRAM, do_gram, &J->qplan[k]);
+      if (e != hipSuccess) return e;
+    }
     ContractCall cc{k, k == 0 && J->pending, true};
     e = timed(J, KC_CONTRACT, do_contract, &cc);
     if (e != hipSuccess) return e;
@@ -940,6 +965,7 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
   build_solve_plans(J);
   for (int k = 0; k < g.N; ++k) {
+    J->merge[k] = merge_gram();
     J->splan[k].stop = J->flag + 1;
     for (int t = 0; t < g.N - 1; ++t) J->pplan[k][t].stop = J->flag + 1;
   }
@@ -1162,6 +1188,10 @@ ifctn_status ifctn_set_option(const char* name, int64_t value) {
   if (!name) return fail(IFCTN_E_INVAL, "name is NULL");
   if (std::strcmp(name, "phased_min") == 0) {
     g_phased_min.store(value < 0 ? -1 : (long long)value);
+    return IFCTN_OK;
+  }
+  if (std::strcmp(name, "merge_gram") == 0) {
+    g_merge_gram.store(value);
     return IFCTN_OK;
   }
   if (std::strcmp(name, "contract_div") == 0) {

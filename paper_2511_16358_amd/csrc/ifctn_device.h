@@ -34,6 +34,107 @@ __device__ __forceinline__ long long eaddr(const EdgeRef e, long long a, long lo
   return e.off + a * e.s1 + b * e.s2;
 }
 
+// --------------------------------------------------------------------------
+// Gram weights Q_{k,i} (see k_gram_q)
+// --------------------------------------------------------------------------
+template <int R>
+__device__ __forceinline__ void gram_work(const double* __restrict__ W64, const double* __restrict__ Gp,
+                                          double* __restrict__ Qp, int nd, int ndd, const QItem it,
+                                          long long item) {
+  constexpr int NP = R * (R + 1) / 2;
+  const int lg = it.lg2P;
+  const long long dd = item >> lg;
+  const int ch = (int)(item & ((1 << lg) - 1));
+  const int Ii = it.Ii;
+  const bool valid = dd < it.D;
+  double acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = 0.0;
+  if (valid) {
+    int im[MAXC];
+    long long t = dd;
+#pragma unroll
+    for (int c = MAXC - 1; c >= 0; --c) {
+      im[c] = 0;
+      if (c < nd) {
+        im[c] = (int)(t % it.ddim[c]);
+        t /= it.ddim[c];
+      }
+    }
+    double sdd = 1.0;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+      if (q < ndd) {
+        const int xa = it.dd_a[q], xb = it.dd_b[q];
+        const int ia = xa == 0 ? im[0] : (xa == 1 ? im[1] : im[2]);
+        const int ib = xb == 0 ? im[0] : (xb == 1 ? im[1] : im[2]);
+        const double w = W64[eaddr(it.edd[q], ia, ib)];
+        sdd *= w * w;
+      }
+    }
+    const int lo = ch * it.CH, hi = min(Ii, lo + it.CH);
+    const double* Gik = Gp + it.gik;
+    constexpr int XU = R <= 6 ? 4 : 2;
+    for (int x0 = lo; x0 < hi; x0 += XU) {
+      double wv[XU][MAXC], g[XU][R];
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int x = min(x0 + u, hi - 1);
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) wv[u][c] = c < nd ? W64[eaddr(it.edi[c], im[c], x)] : 1.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) g[u][r] = Gik[(long long)r * Ii + x];
+      }
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const double live = (x0 + u < hi) ? 1.0 : 0.0;
+        double w = sdd * live;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) w *= wv[u][c] * wv[u][c];
+        int p = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double wr = w * g[u][r];
+#pragma unroll
+          for (int s2 = r; s2 < R; ++s2) acc[p++] += wr * g[u][s2];
+        }
+      }
+    }
+  }
+  for (int o = 1; o < (1 << lg); o <<= 1) {
+#pragma unroll
+    for (int p = 0; p < NP; ++p) acc[p] += __shfl_xor(acc[p], o, 64);
+  }
+  if (valid && ch == 0) {
+    double* q = Qp + it.qoff + dd * NP;
+#pragma unroll
+    for (int p = 0; p < NP; ++p) q[p] = acc[p];
+  }
+}
+
+// One workgroup of Gram weights: block bid of the items of every i != k
+// (constant indices into the records; they come from device memory, a
+// runtime index into the argument block would force a scratch copy).
+__device__ __forceinline__ void gram_block(const GramRef& a, long long bid) {
+  int ii = 0;
+  if (a.ni > 1 && bid >= a.blk0[1]) ii = 1;
+  if (a.ni > 2 && bid >= a.blk0[2]) ii = 2;
+  if (a.ni > 3 && bid >= a.blk0[3]) ii = 3;
+  const long long b0 = ii == 0 ? a.blk0[0] : ii == 1 ? a.blk0[1] : ii == 2 ? a.blk0[2] : a.blk0[3];
+  const long long item = (bid - b0) * NT + threadIdx.x;
+  const QItem it = a.dit[ii];
+  switch (it.R) {   // uniform per workgroup
+    case 1: gram_work<1>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 2: gram_work<2>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 3: gram_work<3>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 4: gram_work<4>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 5: gram_work<5>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 6: gram_work<6>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    case 7: gram_work<7>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+    default: gram_work<8>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
+  }
+}
+
 // Division by a loop-invariant divisor through a float reciprocal: for
 // 0 <= n < 2^22 the estimate trunc(n * (1/d)) is within one of n / d (the two
 // roundings are below 2^-23 relative), and one correction step makes it exact.
@@ -711,6 +812,10 @@ __device__ __forceinline__ void block_norms(double dx2, double x2, double f2, do
 template <typename TX, typename TC, int NC, bool UPD, bool CON, int SPT>
 __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
   if (a.stop && *a.stop) return;
+  if (blockIdx.x < a.gblocks) {           // Gram weights of the same block
+    gram_block(a.gr, blockIdx.x);
+    return;
+  }
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const FLayout Ly = flayout((int)sizeof(TC), a);
   long long* pbase = (long long*)(smem + Ly.pbase);
@@ -724,7 +829,7 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
   TC* Tl = (TC*)(smem + Ly.T);
   double* red = (double*)(smem + Ly.red);
 
-  const int tid = threadIdx.x, bid = blockIdx.x;
+  const int tid = threadIdx.x, bid = blockIdx.x - a.gblocks;   // contraction workgroup index
   const int jt = bid % a.JT, sp = bid / a.JT;
   const int j0 = jt * a.jn, jcnt = min(a.jn, a.Ik - j0);
   const long long p_begin = (long long)sp * a.PPW, p_end = min(a.nplanes, p_begin + a.PPW);
@@ -841,6 +946,10 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
 template <typename TX, typename TC, int NC, int SPT>
 __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
   if (a.stop && *a.stop) return;
+  if (blockIdx.x < a.gblocks) {
+    gram_block(a.gr, blockIdx.x);
+    return;
+  }
   extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
   const FLayout Ly = flayout((int)sizeof(TC), a);
   long long* pbase = (long long*)(smem + Ly.pbase);
@@ -853,7 +962,7 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
   TC* Tl = (TC*)(smem + Ly.T);
   TC* tpart = (TC*)(smem + Ly.tpart);
 
-  const int tid = threadIdx.x, bid = blockIdx.x;
+  const int tid = threadIdx.x, bid = blockIdx.x - a.gblocks;   // contraction workgroup index
   const int jt = bid % a.JT, spf = bid / a.JT;          // partial index = plane split * FS + fibre split
   const int sp = spf / a.FS, fs = spf - sp * a.FS;
   const int j0 = jt * a.jn, jcnt = min(a.jn, a.Ik - j0);
@@ -968,7 +1077,7 @@ static hipError_t contract_dispatch(bool upd, bool con, int spt, const ContractA
 
 template <typename TX, typename TC, int NC>
 static hipError_t fast_dispatch_nc(bool upd, bool con, int spt, const ContractArgs& a, size_t smem, hipStream_t s) {
-  const dim3 grid((unsigned)(a.JT * a.S * a.FS)), blk(NT);
+  const dim3 grid((unsigned)(a.JT * a.S * a.FS + a.gblocks)), blk(NT);
   if (a.kind == 1) {
 #define IFCTN_ROWS(U, C, P)                                                              \
   if (upd == U && con == C && spt == P) {                                                \

@@ -52,6 +52,16 @@ struct QItem {               // one i != k
   EdgeRef edd[3];             // W(i_a, i_b), a, b in d
 };
 
+// What a workgroup of Gram weights needs (device records and buffers)
+struct GramRef {
+  const QItem* dit;
+  int ni, nd, ndd;
+  long long blk0[MAXN];
+  const double* W64;
+  const double* G;
+  double* Q;
+};
+
 struct QArgs {
   int ni, nd, ndd;
   long long blk0[MAXN];       // first workgroup of each i; blk0[ni] = total
@@ -115,6 +125,10 @@ struct ContractArgs {
   double* Upart;         // [S][I_k][Rprod] split partial sums
   double* normpart;      // [blocks][3]: ||dX||^2, ||X||^2, ||X_new - Xhat||^2
   const int* stop;       // device stop flag (every launch of a stopped job is a no-op)
+  // the Gram weights of the same block, computed by gblocks extra workgroups
+  // of the launch (they depend on the same inputs as the contraction)
+  int gblocks;
+  GramRef gr;
 };
 
 // Factor block k (all G_{k,i}, i != k, in ascending i), one workgroup per

@@ -84,104 +84,20 @@ __global__ __launch_bounds__(NT) void k_edge(const double* __restrict__ Gab, con
 // butterfly.  The fibre chunk is walked four entries at a time with all
 // loads issued first.
 // --------------------------------------------------------------------------
-template <int R>
-__device__ __forceinline__ void gram_work(const double* __restrict__ W64, const double* __restrict__ Gp,
-                                          double* __restrict__ Qp, int nd, int ndd, const QItem it,
-                                          long long item) {
-  constexpr int NP = R * (R + 1) / 2;
-  const int lg = it.lg2P;
-  const long long dd = item >> lg;
-  const int ch = (int)(item & ((1 << lg) - 1));
-  const int Ii = it.Ii;
-  const bool valid = dd < it.D;
-  double acc[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) acc[p] = 0.0;
-  if (valid) {
-    int im[MAXC];
-    long long t = dd;
-#pragma unroll
-    for (int c = MAXC - 1; c >= 0; --c) {
-      im[c] = 0;
-      if (c < nd) {
-        im[c] = (int)(t % it.ddim[c]);
-        t /= it.ddim[c];
-      }
-    }
-    double sdd = 1.0;
-#pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      if (q < ndd) {
-        const int xa = it.dd_a[q], xb = it.dd_b[q];
-        const int ia = xa == 0 ? im[0] : (xa == 1 ? im[1] : im[2]);
-        const int ib = xb == 0 ? im[0] : (xb == 1 ? im[1] : im[2]);
-        const double w = W64[eaddr(it.edd[q], ia, ib)];
-        sdd *= w * w;
-      }
-    }
-    const int lo = ch * it.CH, hi = min(Ii, lo + it.CH);
-    const double* Gik = Gp + it.gik;
-    constexpr int XU = R <= 6 ? 4 : 2;
-    for (int x0 = lo; x0 < hi; x0 += XU) {
-      double wv[XU][MAXC], g[XU][R];
-#pragma unroll
-      for (int u = 0; u < XU; ++u) {
-        const int x = min(x0 + u, hi - 1);
-#pragma unroll
-        for (int c = 0; c < MAXC; ++c) wv[u][c] = c < nd ? W64[eaddr(it.edi[c], im[c], x)] : 1.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) g[u][r] = Gik[(long long)r * Ii + x];
-      }
-#pragma unroll
-      for (int u = 0; u < XU; ++u) {
-        const double live = (x0 + u < hi) ? 1.0 : 0.0;
-        double w = sdd * live;
-#pragma unroll
-        for (int c = 0; c < MAXC; ++c) w *= wv[u][c] * wv[u][c];
-        int p = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double wr = w * g[u][r];
-#pragma unroll
-          for (int s2 = r; s2 < R; ++s2) acc[p++] += wr * g[u][s2];
-        }
-      }
-    }
-  }
-  for (int o = 1; o < (1 << lg); o <<= 1) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p) acc[p] += __shfl_xor(acc[p], o, 64);
-  }
-  if (valid && ch == 0) {
-    double* q = Qp + it.qoff + dd * NP;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) q[p] = acc[p];
-  }
-}
 
 __global__ __launch_bounds__(NT) void k_gram_q(QArgs a) {
   if (a.stop && *a.stop) return;
-  // constant indices into the argument block; the per-i records come from
-  // device memory (a runtime index into the argument block would force a
-  // copy of it into scratch memory)
-  const long long bid = blockIdx.x;
-  int ii = 0;
-  if (a.ni > 1 && bid >= a.blk0[1]) ii = 1;
-  if (a.ni > 2 && bid >= a.blk0[2]) ii = 2;
-  if (a.ni > 3 && bid >= a.blk0[3]) ii = 3;
-  const long long b0 = ii == 0 ? a.blk0[0] : ii == 1 ? a.blk0[1] : ii == 2 ? a.blk0[2] : a.blk0[3];
-  const long long item = (bid - b0) * NT + threadIdx.x;
-  const QItem it = a.dit[ii];
-  switch (it.R) {   // uniform per workgroup
-    case 1: gram_work<1>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
-    case 2: gram_work<2>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
-    case 3: gram_work<3>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
-    case 4: gram_work<4>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
-    case 5: gram_work<5>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
-    case 6: gram_work<6>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
-    case 7: gram_work<7>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
-    default: gram_work<8>(a.W64, a.G, a.Q, a.nd, a.ndd, it, item); break;
-  }
+  GramRef r;
+  r.dit = a.dit;
+  r.ni = a.ni;
+  r.nd = a.nd;
+  r.ndd = a.ndd;
+#pragma unroll
+  for (int q = 0; q < MAXN; ++q) r.blk0[q] = a.blk0[q];
+  r.W64 = a.W64;
+  r.G = a.G;
+  r.Q = a.Q;
+  gram_block(r, blockIdx.x);
 }
 // --------------------------------------------------------------------------
 // K5: factor block k: for every i != k (ascending), column j of G_{k,i} by

@@ -116,6 +116,20 @@ def test_fp32_path_matches_oracle(dims, ranks):
     assert np.array_equal(r["Xg"][m], p.O[m].astype(np.float64))
 
 
+@pytest.mark.parametrize("dims,ranks", SMALL[:5], ids=["x".join(map(str, d)) for d, _ in SMALL[:5]])
+def test_separate_gram_launch_matches_oracle(dims, ranks):
+    """The Gram weights as a launch of their own (the default puts them in the
+    contraction launch): same results."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem(dims, ranks, seed=23)
+    ifctn.set_option("merge_gram", 0)
+    try:
+        r = run_both(p, 3, ifctn.IFCTN_FP64)
+    finally:
+        ifctn.set_option("merge_gram", -1)
+    assert relerr(r["Xg"], r["Xo"]) < 1e-10
+
+
 def test_planted30_fp32_20_sweeps():
     """The oracle-sized workload: 30^3, planted R=2, 50% sampling, 20 sweeps."""
     from paper_2511_16358_amd import ifctn
