@@ -301,7 +301,17 @@ ContractPlan plan_contract(const Geo& g, int k) {
     while ((long long)spt * NT < slots) spt *= 2;
     P.spt = spt;
     P.smem = contract_smem_bytes(g.dtype, a);
-    return P;
+    if (spt <= 8) return P;
+    // more than 8 accumulator slots per thread (very large Rprod): the
+    // layout-specialised kernels are built for at most 8; plan the generic one
+    a.kind = 0;
+    a.plfast = 0;
+    a.FS = 1;
+    a.fch = 1;
+    a.psplit = 1;
+    a.stage = 0;
+    a.cdl = a.Rl = a.Rc2 = 0;
+    a.gloff = 0;
   }
 
   // generic layout: an LDS tile of at most `tile` streaming elements, at

@@ -64,6 +64,7 @@ SMALL = [
     ((3, 1, 4), W.uniform_ranks(3, 2)),          # a mode of size 1
     ((12, 20, 3, 9), np.array([[0, 2, 3, 1], [2, 0, 2, 3], [3, 2, 0, 2], [1, 3, 2, 0]])),
     ((8, 7, 9, 6, 10), W.uniform_ranks(5, 3)),   # order 5: staged accumulation over two c-modes
+    ((4, 4, 4, 4, 4), W.uniform_ranks(5, 8)),    # largest rank at order 5: 8^4 accumulators per row
 ]
 
 

@@ -19,7 +19,7 @@ SHAPES = [
     ((30, 30, 30), 2), ((256, 256, 31), 6), ((214, 61, 144), 4), ((144, 176, 3, 50), 5),
     ((7, 13, 5), 3), ((9, 11), 4), ((5, 6, 7, 3), 2), ((4, 3, 5, 2, 3), 2), ((1, 1, 1), 1),
     ((3, 1, 4), 2), ((17, 33, 9), 8), ((144, 176, 50, 3), 5), ((16, 16, 16, 16, 16), 6),
-    ((45, 44, 46, 43), 4), ((20, 19, 21, 18, 22), 6),
+    ((45, 44, 46, 43), 4), ((20, 19, 21, 18, 22), 6), ((4, 4, 4, 4, 4), 8),
 ]
 
 PLAN_RE = re.compile(r"\[ifctn plan\] (.*?) \|")
@@ -191,6 +191,8 @@ def test_contract_plan_covers_tensor_once(dims, R):
             assert np.all(ucount == 1), plan
             assert int(plan["smem"]) <= 64 * 1024
             assert int(plan["spt"]) * 256 >= int(plan["jn"]) * int(plan["Rprod"])
+            if int(plan["kind"]) != 0:
+                assert int(plan["spt"]) <= 8        # the layout-specialised kernels are built for <= 8
             if int(plan["stage"]):
                 # staged accumulation: every batch and workgroup holds whole
                 # groups of the last c-mode, so the group products line up
