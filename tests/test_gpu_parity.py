@@ -357,3 +357,36 @@ def test_full_size_lemma2_every_sweep(name):
         assert dec >= need - 1e-5 * F, (s, dec, need)
         F = st["objective"]
     job.close()
+
+
+def _random_case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    N = int(rng.integers(2, 6))
+    while True:
+        dims = tuple(int(x) for x in rng.integers(1, 14, size=N))
+        if np.prod(dims) <= 4000:
+            break
+    ranks = np.zeros((N, N), dtype=np.int64)
+    for a in range(N):
+        for b in range(a + 1, N):
+            ranks[a][b] = ranks[b][a] = int(rng.integers(1, 9 if N <= 3 else 6))
+    return dims, ranks
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_shapes_fp64(seed):
+    """Random orders 2-5, mode sizes 1-13 and unequal edge ranks 1-8: two
+    FP64 sweeps against the oracle (every other case with the phased factor
+    blocks forced)."""
+    from paper_2511_16358_amd import ifctn
+    dims, ranks = _random_case(seed)
+    p = W.random_problem(dims, ranks, seed=seed, keep=0.6)
+    if seed % 2:
+        ifctn.set_option("phased_min", 0)
+    try:
+        r = run_both(p, 2, ifctn.IFCTN_FP64)
+    finally:
+        ifctn.set_option("phased_min", -1)
+    assert relerr(r["Xg"], r["Xo"]) < 1e-10, (dims, ranks.tolist())
+    for key in r["Go"]:
+        assert relerr(r["Gg"][key], r["Go"][key]) < 1e-9, (key, dims)
