@@ -40,7 +40,7 @@ def parse():
     ap.add_argument("--serve-precision", default="bf16", choices=["fp32", "bf16"])
     ap.add_argument("--serve-budget-gb", type=float, default=64.0)
     ap.add_argument("--serve-slots", type=int, default=16)
-    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-streams", type=int, default=16)
     ap.add_argument("--serve-round", type=int, default=10)
     ap.add_argument("--no-tuning", action="store_true", help="skip the rank-grid tuning leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")

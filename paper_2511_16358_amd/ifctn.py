@@ -289,7 +289,7 @@ class Server:
     tensors (or numpy arrays, copied to the device); the binding keeps them
     and the output tensor alive until the completion is polled."""
 
-    def __init__(self, hbm_budget_bytes, max_active=8, num_streams=4, sweeps_per_round=10, device=None):
+    def __init__(self, hbm_budget_bytes, max_active=8, num_streams=8, sweeps_per_round=10, device=None):
         cfg = IfctnServerConfig()
         cfg.hbm_budget_bytes = int(hbm_budget_bytes)
         cfg.max_active, cfg.num_streams = int(max_active), int(num_streams)
