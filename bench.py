@@ -257,7 +257,8 @@ def rank_grid_run(ifctn, torch, p, grids, t_max=1000, eps=1e-5, precision=None):
     M = torch.as_tensor(p.mask).cuda()
     G0s = [W.initial_factors_for(p, r, seed=100 + q) for q, r in enumerate(grids)]
     need = sum(ifctn.workspace_bytes(p.dims, r, prec) for r in grids)
-    srv = ifctn.Server(int(need * 1.2) + (64 << 20), max_active=len(grids), num_streams=4, sweeps_per_round=10)
+    srv = ifctn.Server(int(need * 1.2) + (64 << 20), max_active=len(grids), num_streams=min(16, len(grids)),
+                       sweeps_per_round=10)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for q, (r, G0) in enumerate(zip(grids, G0s)):

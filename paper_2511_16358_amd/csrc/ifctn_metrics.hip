@@ -47,24 +47,37 @@ __global__ __launch_bounds__(MT) void k_band_sqerr(const T* __restrict__ X, cons
   if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = s;
 }
 
-// SSIM map of band b summed over a range of window positions
+// SSIM map of band b (grid.y) over one 16 x 16 tile of window positions
+// (grid.x): the 26 x 26 patch of both images is staged in LDS once, then each
+// thread forms the weighted moments of its window from LDS.
+constexpr int ST = 16;                 // output tile edge
+constexpr int SP = ST + WIN - 1;       // staged patch edge
+
 template <typename T>
 __global__ __launch_bounds__(MT) void k_band_ssim(const T* __restrict__ X, const T* __restrict__ Y, int H, int W,
                                                   int B, double c1, double c2, double* __restrict__ part) {
   __shared__ double red[MT / 64];
+  __shared__ double px[SP * SP], py[SP * SP];
   const int b = blockIdx.y;
   const int Hv = H - WIN + 1, Wv = W - WIN + 1;
-  const long long nv = (long long)Hv * Wv;
+  const int tw = (Wv + ST - 1) / ST;
+  const int th0 = (int)(blockIdx.x / tw) * ST, tw0 = (int)(blockIdx.x % tw) * ST;
+  for (int e = threadIdx.x; e < SP * SP; e += MT) {
+    const int y = min(th0 + e / SP, H - 1), x = min(tw0 + e % SP, W - 1);   // clamped: unused past the edge
+    const long long o = ((long long)y * W + x) * B + b;
+    px[e] = (double)X[o];
+    py[e] = (double)Y[o];
+  }
+  __syncthreads();
+  const int ly = threadIdx.x / ST, lx = threadIdx.x % ST;
   double acc = 0.0;
-  for (long long p = (long long)blockIdx.x * MT + threadIdx.x; p < nv; p += (long long)gridDim.x * MT) {
-    const int h0 = (int)(p / Wv), w0 = (int)(p - (long long)h0 * Wv);
+  if (th0 + ly < Hv && tw0 + lx < Wv) {
     double mx = 0.0, my = 0.0, sxx = 0.0, syy = 0.0, sxy = 0.0;
     for (int dy = 0; dy < WIN; ++dy) {
-      const long long row = ((long long)(h0 + dy) * W + w0) * B + b;
 #pragma unroll
       for (int dx = 0; dx < WIN; ++dx) {
         const double g = c_win[dy * WIN + dx];
-        const double x = (double)X[row + (long long)dx * B], y = (double)Y[row + (long long)dx * B];
+        const double x = px[(ly + dy) * SP + lx + dx], y = py[(ly + dy) * SP + lx + dx];
         mx += g * x;
         my += g * y;
         sxx += g * x * x;
@@ -73,7 +86,7 @@ __global__ __launch_bounds__(MT) void k_band_ssim(const T* __restrict__ X, const
       }
     }
     const double vx = sxx - mx * mx, vy = syy - my * my, cxy = sxy - mx * my;
-    acc += ((2.0 * mx * my + c1) * (2.0 * cxy + c2)) / ((mx * mx + my * my + c1) * (vx + vy + c2));
+    acc = ((2.0 * mx * my + c1) * (2.0 * cxy + c2)) / ((mx * mx + my * my + c1) * (vx + vy + c2));
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0) part[(long long)b * gridDim.x + blockIdx.x] = s;
@@ -115,7 +128,7 @@ extern "C" ifctn_status ifctn_image_metrics(const void* X_dev, const void* ref_d
   const long long HW = H * W;
   const long long nv = (H - WIN + 1) * (W - WIN + 1);
   const int nb_e = (int)std::min<long long>(64, (HW + MT - 1) / MT);
-  const int nb_s = (int)std::min<long long>(256, (nv + MT - 1) / MT);
+  const int nb_s = (int)(((H - WIN + 1 + ST - 1) / ST) * ((W - WIN + 1 + ST - 1) / ST));   // output tiles
   double* buf = nullptr;
   const size_t n_part = (size_t)B * (nb_e + nb_s), n_out = 2 * (size_t)B;
   if (hipMalloc((void**)&buf, (n_part + n_out) * sizeof(double)) != hipSuccess)
