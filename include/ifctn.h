@@ -243,6 +243,11 @@ ifctn_status ifctn_image_metrics(const void* X_dev, const void* ref_dev, int64_t
  *   holds at least this many entries; the one-workgroup-per-column form
  *   otherwise.  Both give the same solution of eq. (updateG) up to rounding.
  *   value < 0 restores the default (16384).
+ *   "phased_onelaunch": 1 runs each sub-block of a phased block as one launch
+ *   (the last workgroup of a column tile to finish its partial sums solves
+ *   the tile's columns); default (value <= 0): two launches per sub-block.
+ *   "merge_gram": 0 computes the Gram weights in a launch of their own
+ *   instead of as extra workgroups of the contraction launch (default).
  *   "contract_div", "contract_emin": a contraction workgroup covers about
  *   max(contract_emin, nX / contract_div) tensor entries (defaults 1280 and
  *   2048; values <= 0 restore them).

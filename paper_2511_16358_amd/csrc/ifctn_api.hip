@@ -157,7 +157,8 @@ struct ContractPlan {
 constexpr int kTargetBlocks = 1024;
 
 // tuning options (ifctn_set_option): < 0 = default
-std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1};
+std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1}, g_onelaunch{-1};
+bool phased_onelaunch() { return g_onelaunch.load() > 0; }   // off by default: measured slower
 bool merge_gram() { return g_merge_gram.load() != 0; }
 long long contract_div() { long long v = g_contract_div.load(); return v > 0 ? v : 1280; }
 long long contract_emin() { long long v = g_contract_emin.load(); return v > 0 ? v : 2048; }
@@ -475,6 +476,8 @@ struct ifctn_job {
   double* Upart = nullptr;
   double* Ufin = nullptr;
   double* Hpart = nullptr;
+  int* hcnt = nullptr;
+  bool onelaunch = true;       // phased blocks: one launch per sub-block
   double* normpart = nullptr;
   double* dgpart = nullptr;
   double* stats5 = nullptr;
@@ -500,7 +503,7 @@ struct ifctn_job {
 namespace {
 
 struct Sizes {
-  size_t x, xb, bits, G, W64, Wc, Q, Upart, Ufin, Hpart, normpart, dgpart, stats, flag, qitems, total;
+  size_t x, xb, bits, G, W64, Wc, Q, Upart, Ufin, Hpart, hcnt, normpart, dgpart, stats, flag, qitems, total;
 };
 
 // A factor block takes the phased form when one of its Gram weight sets is
@@ -570,12 +573,15 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
   s.Upart = al256(upmax * 8);
   s.Ufin = al256(ufmax * 8);
   s.Hpart = al256(hmax * 8);
+  long long ikmax = 1;
+  for (int k = 0; k < g.N; ++k) ikmax = std::max<long long>(ikmax, g.dims[k]);
+  s.hcnt = al256(ikmax * 4);              // one arrival counter per column tile
   s.normpart = al256(nnorm * 3 * 8);
   s.dgpart = al256(ndg * 8);
   s.stats = al256(8 * 8);
   s.flag = al256(16);
   s.qitems = al256(sizeof(QItem) * MAXN * (MAXN - 1));
-  s.total = s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.Hpart + s.normpart + s.dgpart +
+  s.total = s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.Hpart + s.hcnt + s.normpart + s.dgpart +
             s.stats + s.flag +
             s.qitems;
   return s;
@@ -673,6 +679,7 @@ void build_solve_plans(ifctn_job* J) {
       h.KS = (int)((h.B.D + HP_DC - 1) / HP_DC);
       h.Ufin = J->Ufin;
       h.Hpart = J->Hpart;
+      h.cnt = J->hcnt;
       h.W64 = J->W64;
       h.Wc = J->Wc;
       h.G = J->G;
@@ -747,8 +754,15 @@ hipError_t do_solve(ifctn_job* J, const void* c) {
   if (!J->phased[k]) return launch_solve(J->g.dtype, *a, J->stream);
   hipError_t e = launch_urow(*a, J->Ufin, J->stream);
   for (int t = 0; t < a->nsub && e == hipSuccess; ++t) {
-    e = launch_hpart(J->pplan[k][t], J->stream);
-    if (e == hipSuccess) e = launch_solve_col(J->g.dtype, J->pplan[k][t], J->stream);
+    if (J->onelaunch) {
+      PhaseArgs h = J->pplan[k][t];
+      h.JW = std::min(h.JW, HS_JW);
+      h.JT = (h.Ik + h.JW - 1) / h.JW;
+      e = launch_hsolve(J->g.dtype, h, J->stream);
+    } else {
+      e = launch_hpart(J->pplan[k][t], J->stream);
+      if (e == hipSuccess) e = launch_solve_col(J->g.dtype, J->pplan[k][t], J->stream);
+    }
   }
   return e;
 }
@@ -951,6 +965,7 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   J->Upart = (double*)p;         p += s.Upart;
   J->Ufin = (double*)p;          p += s.Ufin;
   J->Hpart = (double*)p;         p += s.Hpart;
+  J->hcnt = (int*)p;             p += s.hcnt;
   J->normpart = (double*)p;      p += s.normpart;
   J->dgpart = (double*)p;        p += s.dgpart;
   J->stats5 = (double*)p;        p += s.stats;
@@ -974,6 +989,7 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   }
   J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
   build_solve_plans(J);
+  J->onelaunch = phased_onelaunch();
   for (int k = 0; k < g.N; ++k) {
     J->merge[k] = merge_gram();
     J->splan[k].stop = J->flag + 1;
@@ -1001,6 +1017,7 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   INIT_TRY(hipMemsetAsync(J->normpart, 0, s.normpart, J->stream));
   INIT_TRY(hipMemsetAsync(J->dgpart, 0, s.dgpart, J->stream));
   INIT_TRY(hipMemsetAsync(J->flag, 0, s.flag, J->stream));
+  INIT_TRY(hipMemsetAsync(J->hcnt, 0, s.hcnt, J->stream));
   INIT_TRY(hipMemcpyAsync(J->G, G0_host, g.nG * 8, hipMemcpyHostToDevice, J->stream));
   for (int k = 0; k < g.N; ++k)
     INIT_TRY(hipMemcpyAsync((void*)J->qplan[k].dit, J->qplan[k].it, sizeof(QItem) * (MAXN - 1),
@@ -1198,6 +1215,10 @@ ifctn_status ifctn_set_option(const char* name, int64_t value) {
   if (!name) return fail(IFCTN_E_INVAL, "name is NULL");
   if (std::strcmp(name, "phased_min") == 0) {
     g_phased_min.store(value < 0 ? -1 : (long long)value);
+    return IFCTN_OK;
+  }
+  if (std::strcmp(name, "phased_onelaunch") == 0) {
+    g_onelaunch.store(value);
     return IFCTN_OK;
   }
   if (std::strcmp(name, "merge_gram") == 0) {

@@ -175,6 +175,7 @@ struct SolveArgs {
 // b_j, solves and refreshes row j of W_{k,i}.  The Gauss-Seidel order over i
 // is kept by launching the sub-blocks one after another.
 constexpr int HP_JW = 32;     // max columns per k_hpart workgroup (power of two)
+constexpr int HS_JW = 4;      // columns per workgroup of the one-launch form (one wave each)
 constexpr int HP_DC = 112;    // d per k_hpart workgroup
 
 struct PhaseArgs {
@@ -189,6 +190,7 @@ struct PhaseArgs {
   int JW, JT, KS;             // column tile, column tiles, d ranges
   const double* Ufin;         // [Ik][Rprod]
   double* Hpart;              // [KS][Ik][np]
+  int* cnt;                   // [JT] arrival counters of the one-launch form (zero between launches)
   double* W64;
   void* Wc;
   double* G;
@@ -237,6 +239,9 @@ size_t solve_smem_bytes(const SolveArgs& a);
 hipError_t launch_urow(const SolveArgs& a, double* Ufin, hipStream_t s);
 hipError_t launch_hpart(const PhaseArgs& a, hipStream_t s);
 hipError_t launch_solve_col(int dtype, const PhaseArgs& a, hipStream_t s);
+// one launch per sub-block: partial H as k_hpart, then the last workgroup of
+// each column tile (a.JW <= 4) reduces and solves its columns, one wave each
+hipError_t launch_hsolve(int dtype, const PhaseArgs& a, hipStream_t s);
 hipError_t launch_reconstruct(int dtype, const ReconArgs& a, hipStream_t s);
 // Stop test of Algorithm 1 on the device, after an X step: reduces the
 // partial norms like launch_finalize and, unless state[0] (stop flag) is

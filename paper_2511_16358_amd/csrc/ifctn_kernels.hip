@@ -589,6 +589,161 @@ __global__ __launch_bounds__(NT) void k_solve_col(PhaseArgs a) {
   }
 }
 
+// One launch per sub-block of a phased factor block.  Every workgroup forms
+// the partial H_j of its d range for its (at most 4) columns, as k_hpart, and
+// counts itself in; the last workgroup of a column tile to arrive -- all
+// partials of the tile are then written and visible -- reduces and solves the
+// tile's columns, one wave per column: the partials in a fixed order, b_j,
+// the LDL^T solve on one lane, the refresh of row j of W_{k,i}.  No
+// workgroup ever waits for another.
+template <int R, typename TC>
+__global__ __launch_bounds__(NT) void k_hsolve(PhaseArgs a) {
+  if (a.stop && *a.stop) return;
+  constexpr int NP = R * (R + 1) / 2;
+  constexpr int NW = NT / 64;
+  __shared__ double sm[HS_JW * HP_DC + HP_DC * MAXP];
+  __shared__ double fH[NW][64], fB[NW][64], Hs[NW][MAXP], bs[NW][MAXR], gold[NW][MAXR], gnew[NW][MAXR];
+  __shared__ int last;
+  const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
+  const int jt = blockIdx.x % a.JT, ks = blockIdx.x / a.JT;
+  const int JW = a.JW;                     // power of two <= HS_JW
+  const int j0 = jt * JW, jcnt = min(JW, a.Ik - j0);
+  const SubBlock& B = a.B;
+  {
+    double* wL = sm;
+    double* qL = sm + HS_JW * HP_DC;
+    const long long dlo = (long long)ks * HP_DC;
+    const int dn = (int)min((long long)HP_DC, B.D - dlo);
+    const double* __restrict__ Q = B.Q + dlo * NP;
+    for_batched<4>(dn * NP, [&](int e) { return Q[e]; }, [&](int e, double v) { qL[e] = v; });
+    const int nd = B.nd;
+    for_batched<2>(
+        jcnt * dn,
+        [&](int e) {
+          const int jl = e / dn;
+          long long x = dlo + (e - jl * dn);
+          double w = 1.0;
+#pragma unroll
+          for (int c = MAXC - 1; c >= 0; --c) {
+            if (c < nd) {
+              const int dim = B.ddim[c];
+              const long long xq = x / dim;
+              const double v = a.W64[eaddr(a.edm[c], j0 + jl, x - xq * dim)];
+              x = xq;
+              w *= v * v;
+            }
+          }
+          return w;
+        },
+        [&](int e, double w) { wL[e] = w; });
+    __syncthreads();
+    const int DS = NT / JW;
+    const int jl = tid % JW, ds = tid / JW;
+    double h[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) h[p] = 0.0;
+    if (jl < jcnt) {
+      for (int dd = ds; dd < dn; dd += DS) {
+        const double w = wL[jl * dn + dd];
+        const double* q = qL + dd * NP;
+#pragma unroll
+        for (int p = 0; p < NP; ++p) h[p] += w * q[p];
+      }
+    }
+    for (int o = JW; o < 64; o <<= 1) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) h[p] += __shfl_xor(h[p], o, 64);
+    }
+    __syncthreads();
+    double* red = sm;                      // [NW][JW][NP]
+    if (lane < JW) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) red[(wv * JW + lane) * NP + p] = h[p];
+    }
+    __syncthreads();
+    for (int e = tid; e < jcnt * NP; e += NT) {
+      const int j2 = e / NP, p = e - j2 * NP;
+      double v = 0.0;
+      for (int w = 0; w < NW; ++w) v += red[(w * JW + j2) * NP + p];
+      a.Hpart[((long long)ks * a.Ik + j0 + j2) * NP + p] = v;
+    }
+  }
+  // arrival: this workgroup's partials are released before it counts in
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) last = atomicAdd(&a.cnt[jt], 1) == a.KS - 1 ? 1 : 0;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();                         // acquire: every partial of the tile is visible
+  double* G = a.G;
+  const int Ik = a.Ik;
+  const bool mine = wv < jcnt;             // wave wv finishes column j0 + wv
+  const int j = j0 + (mine ? wv : 0);
+  // H_j: lane (p, c) sums the ranges q = c mod cq in ascending order
+  const int cq = 64 / NP;
+  const int p_me = lane % NP, c_me = lane / NP;
+  double hs = 0.0;
+  if (mine && c_me < cq)
+    for (int q = c_me; q < a.KS; q += cq) hs += a.Hpart[((long long)q * Ik + j) * NP + p_me];
+  // b_j: lane (r, c) sums the terms o = c mod cb in ascending order
+  const int nother = a.Rprod / R;
+  const int cb = min(64 / R, nother);
+  const int r_me = lane % R, o_me = lane / R;
+  double bv = 0.0;
+  if (mine && o_me < cb) {
+    const double* u = a.Ufin + (long long)j * a.Rprod;
+    for (int o = o_me; o < nother; o += cb) {
+      int rem = o;
+      long long col = (long long)r_me * a.ustride[B.upos];
+      double coef = 1.0;
+      for (int q = a.nu - 1; q >= 0; --q) {
+        if (q == B.upos) continue;
+        const int r = rem % a.urank[q];
+        rem /= a.urank[q];
+        col += (long long)r * a.ustride[q];
+        coef *= G[a.ugoff[q] + (long long)r * Ik + j];
+      }
+      bv += coef * u[col];
+    }
+  }
+  fH[wv][lane] = (mine && c_me < cq) ? hs : 0.0;
+  fB[wv][lane] = (mine && o_me < cb) ? bv : 0.0;
+  __syncthreads();
+  if (mine) {
+    if (lane < NP) {
+      double sum = 0.0;
+      for (int c = 0; c < cq; ++c) sum += fH[wv][c * NP + lane];
+      Hs[wv][lane] = sum;
+    } else if (lane >= 48 && lane < 48 + R) {
+      const int r = lane - 48;
+      double sum = 0.0;
+      for (int c = 0; c < cb; ++c) sum += fB[wv][c * R + r];
+      gold[wv][r] = G[B.goff_ki + (long long)r * Ik + j];
+      bs[wv][r] = sum + a.rho * gold[wv][r];
+    }
+  }
+  __syncthreads();
+  if (mine && lane == 0) {
+    const double dg = ldlt_solve<R>(Hs[wv], bs[wv], a.rho, gold[wv], gnew[wv]);
+    for (int r = 0; r < R; ++r) G[B.goff_ki + (long long)r * Ik + j] = gnew[wv][r];
+    a.dgpart[(long long)a.t * Ik + j] = dg;
+  }
+  __syncthreads();
+  if (mine) {
+    TC* Wc = (TC*)a.Wc;
+    const double* Gik = G + B.goff_ik;
+    for (int y = lane; y < B.Ii; y += 64) {
+      double sum = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) sum += gnew[wv][r] * Gik[(long long)r * B.Ii + y];
+      const long long ad = B.w_off + (long long)j * B.w_sj + (long long)y * B.w_sy;
+      a.W64[ad] = sum;
+      Wc[ad] = (TC)sum;
+    }
+  }
+  if (tid == 0) a.cnt[jt] = 0;             // ready for the next launch (stream order)
+}
+
 // --------------------------------------------------------------------------
 // K8: dense reconstruction eq. (iFCTN) = product of all edge matrices
 // --------------------------------------------------------------------------
@@ -770,6 +925,27 @@ hipError_t launch_solve_col(int dtype, const PhaseArgs& a, hipStream_t s) {
   else
     IFCTN_GO(k_solve_col<double>, dim3((unsigned)a.Ik), dim3(NT), 0, s, a);
   return hipGetLastError();
+}
+
+template <typename TC>
+static hipError_t hsolve_dispatch(const PhaseArgs& a, hipStream_t s) {
+  const dim3 grid((unsigned)(a.JT * a.KS)), blk(NT);
+  switch (a.B.R) {
+    case 1: IFCTN_GO((k_hsolve<1, TC>), grid, blk, 0, s, a); break;
+    case 2: IFCTN_GO((k_hsolve<2, TC>), grid, blk, 0, s, a); break;
+    case 3: IFCTN_GO((k_hsolve<3, TC>), grid, blk, 0, s, a); break;
+    case 4: IFCTN_GO((k_hsolve<4, TC>), grid, blk, 0, s, a); break;
+    case 5: IFCTN_GO((k_hsolve<5, TC>), grid, blk, 0, s, a); break;
+    case 6: IFCTN_GO((k_hsolve<6, TC>), grid, blk, 0, s, a); break;
+    case 7: IFCTN_GO((k_hsolve<7, TC>), grid, blk, 0, s, a); break;
+    default: IFCTN_GO((k_hsolve<8, TC>), grid, blk, 0, s, a); break;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_hsolve(int dtype, const PhaseArgs& a, hipStream_t s) {
+  if (a.JW > HS_JW) return hipErrorInvalidValue;
+  return dtype == 0 ? hsolve_dispatch<float>(a, s) : hsolve_dispatch<double>(a, s);
 }
 
 hipError_t launch_reconstruct(int dtype, const ReconArgs& a, hipStream_t s) {

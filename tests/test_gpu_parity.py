@@ -117,6 +117,22 @@ def test_fp32_path_matches_oracle(dims, ranks):
     assert np.array_equal(r["Xg"][m], p.O[m].astype(np.float64))
 
 
+@pytest.mark.parametrize("dims,ranks", SMALL, ids=["x".join(map(str, d)) for d, _ in SMALL])
+def test_phased_one_launch_form_matches_oracle(dims, ranks):
+    """Phased factor blocks in the one-launch form (the last workgroup of a
+    column tile solves its columns); the default is two launches per sub-block."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem(dims, ranks, seed=29)
+    ifctn.set_option("phased_min", 0)
+    ifctn.set_option("phased_onelaunch", 1)
+    try:
+        r = run_both(p, 3, ifctn.IFCTN_FP64)
+    finally:
+        ifctn.set_option("phased_min", -1)
+        ifctn.set_option("phased_onelaunch", -1)
+    assert relerr(r["Xg"], r["Xo"]) < 1e-10
+
+
 @pytest.mark.parametrize("dims,ranks", SMALL[:5], ids=["x".join(map(str, d)) for d, _ in SMALL[:5]])
 def test_separate_gram_launch_matches_oracle(dims, ranks):
     """The Gram weights as a launch of their own (the default puts them in the
