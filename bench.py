@@ -242,7 +242,7 @@ def serve_mix(ifctn, torch, args):
             "server": {"hbm_budget_gb": args.serve_budget_gb, "slots": args.serve_slots,
                        "streams": args.serve_streams, "sweeps_per_round": args.serve_round},
             "input_generation_s": round(t_gen, 2),
-            "mix": "512 requests, Poisson arrivals at 200/s, orders 3-5, modes 16-256 (<= 4,194,304 entries), "
+            "mix": f"{len(specs)} requests, Poisson arrivals at 200/s, orders 3-5, modes 16-256 (<= 4,194,304 entries), "
                    "R in 2..6, sampling 5/10/30%, planted iFCTN N(0,1) unit max + N(0,0.01^2), "
                    "t_max 100, eps 1e-5"}
 
