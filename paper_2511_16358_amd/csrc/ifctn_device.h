@@ -159,6 +159,23 @@ __device__ __forceinline__ int fdivmod(int n, const FDiv f, int* rem) {
   return q;
 }
 
+// s + term(0, load(0)) + ... + term(n-1, load(n-1)), added in ascending u, with
+// the loads issued U at a time: a batch's loads are all in flight before its
+// first term is added, and a short last batch clamps its indices (in bounds,
+// results unused), so n loads take ceil(n / U) round trips, not a serial tail.
+template <int U, typename Load, typename Term>
+__device__ __forceinline__ double ordered_sum(double s, int n, Load load, Term term) {
+  for (int u0 = 0; u0 < n; u0 += U) {
+    double v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = load(min(u0 + u, n - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (u0 + u < n) s += term(u0 + u, v[u]);
+  }
+  return s;
+}
+
 // for (e = tid; e < n; e += NT) use(e, load(e)), with the loads of U
 // consecutive iterations issued before any of them is consumed (the index is
 // clamped so that every load is in bounds and the body has no branches)

@@ -189,15 +189,9 @@ __device__ __forceinline__ void urow_reduce(const SolveArgs& a, int j, double* p
     if (c < nch) {
       const double* up = a.Upart + (long long)j * a.Rprod + col;
       const long long stride = (long long)Ik * a.Rprod;
-      int q = c;
-      for (; q + 15 * nch < a.S; q += 16 * nch) {
-        double x[16];
-#pragma unroll
-        for (int w = 0; w < 16; ++w) x[w] = up[(long long)(q + w * nch) * stride];
-#pragma unroll
-        for (int w = 0; w < 16; ++w) v += x[w];
-      }
-      for (; q < a.S; q += nch) v += up[(long long)q * stride];
+      v = ordered_sum<16>(
+          0.0, (a.S - c + nch - 1) / nch, [&](int u) { return up[(long long)(c + u * nch) * stride]; },
+          [](int, double x) { return x; });
     }
     part[tid] = v;
     __syncthreads();
@@ -210,17 +204,8 @@ __device__ __forceinline__ void urow_reduce(const SolveArgs& a, int j, double* p
     for (int col = tid; col < a.Rprod; col += NT) {
       const double* up = a.Upart + (long long)j * a.Rprod + col;
       const long long stride = (long long)Ik * a.Rprod;
-      double sum = 0.0;
-      int q = 0;
-      for (; q + 7 < a.S; q += 8) {
-        double x[8];
-#pragma unroll
-        for (int w = 0; w < 8; ++w) x[w] = up[(long long)(q + w) * stride];
-#pragma unroll
-        for (int w = 0; w < 8; ++w) sum += x[w];
-      }
-      for (; q < a.S; ++q) sum += up[(long long)q * stride];
-      u[col] = sum;
+      u[col] = ordered_sum<16>(
+          0.0, a.S, [&](int q) { return up[(long long)q * stride]; }, [](int, double x) { return x; });
     }
   }
 }
@@ -310,15 +295,12 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
           const int e = c_me + u * cpp;
           if (e < nd_t) hacc += wl[e] * qv[u];
         }
-        int e = c_me + 8 * cpp;
-        for (; e + 7 * cpp < nd_t; e += 8 * cpp) {
-          double q2[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) q2[u] = qp[(long long)(e + u * cpp) * np];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) hacc += wl[e + u * cpp] * q2[u];
-        }
-        for (; e < nd_t; e += cpp) hacc += wl[e] * qp[(long long)e * np];
+        // the rest of this thread's d (c_me + u cpp, u >= 8), ascending
+        const int e8 = c_me + 8 * cpp;
+        hacc = ordered_sum<16>(
+            hacc, e8 < nd_t ? (nd_t - e8 + cpp - 1) / cpp : 0,
+            [&](int u) { return qp[(long long)(e8 + u * cpp) * np]; },
+            [&](int u, double q) { return wl[e8 + u * cpp] * q; });
       }
       if (d0 + TD < B.D) __syncthreads();
     }
@@ -512,15 +494,9 @@ __global__ __launch_bounds__(NT) void k_solve_col(PhaseArgs a) {
   if (c_me < cpp) {
     const double* hp = a.Hpart + (long long)j * np + p_me;
     const long long stride = (long long)Ik * np;
-    int q = c_me;
-    for (; q + 7 * cpp < a.KS; q += 8 * cpp) {
-      double x[8];
-#pragma unroll
-      for (int w = 0; w < 8; ++w) x[w] = hp[(long long)(q + w * cpp) * stride];
-#pragma unroll
-      for (int w = 0; w < 8; ++w) hacc += x[w];
-    }
-    for (; q < a.KS; q += cpp) hacc += hp[(long long)q * stride];
+    hacc = ordered_sum<16>(
+        0.0, (a.KS - c_me + cpp - 1) / cpp, [&](int u) { return hp[(long long)(c_me + u * cpp) * stride]; },
+        [](int, double x) { return x; });
   }
   __syncthreads();                       // gk complete
   const int nother = a.Rprod / R;
