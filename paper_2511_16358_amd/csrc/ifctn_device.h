@@ -37,6 +37,58 @@ __device__ __forceinline__ long long eaddr(const EdgeRef e, long long a, long lo
 // --------------------------------------------------------------------------
 // Gram weights Q_{k,i} (see k_gram_q)
 // --------------------------------------------------------------------------
+// Rows [R0, R1) of the packed upper triangle of Q(dd) for one d: every lane of
+// a group of 2^lg lanes sums a chunk of the far-side mode x, the group adds its
+// chunks by a fixed butterfly, and lane 0 of the group stores the entries.
+// Splitting the rows over passes keeps the accumulators few, so that the
+// contraction launch these workgroups ride in keeps its occupancy.
+template <int R, int R0, int R1, int XU>
+__device__ __forceinline__ void gram_rows(const double* __restrict__ W64, const double* __restrict__ Gik,
+                                          double* __restrict__ q, int nd, const QItem& it, const int* im,
+                                          double sdd, bool valid, int lo, int hi, int lg, int Ii, bool store) {
+  constexpr int P0 = R0 * R - R0 * (R0 - 1) / 2;      // packed index of (R0, R0)
+  constexpr int P1 = R1 * R - R1 * (R1 - 1) / 2;
+  constexpr int NQ = P1 - P0;
+  double acc[NQ];
+#pragma unroll
+  for (int p = 0; p < NQ; ++p) acc[p] = 0.0;
+  if (valid) {
+    for (int x0 = lo; x0 < hi; x0 += XU) {
+      double wv[XU][MAXC], g[XU][R];
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const int x = min(x0 + u, hi - 1);
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) wv[u][c] = c < nd ? W64[eaddr(it.edi[c], im[c], x)] : 1.0;
+#pragma unroll
+        for (int r = R0; r < R; ++r) g[u][r] = Gik[(long long)r * Ii + x];
+      }
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+        const double live = (x0 + u < hi) ? 1.0 : 0.0;
+        double w = sdd * live;
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) w *= wv[u][c] * wv[u][c];
+        int p = 0;
+#pragma unroll
+        for (int r = R0; r < R1; ++r) {
+          const double wr = w * g[u][r];
+#pragma unroll
+          for (int s2 = r; s2 < R; ++s2) acc[p++] += wr * g[u][s2];
+        }
+      }
+    }
+  }
+  for (int o = 1; o < (1 << lg); o <<= 1) {
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) acc[p] += __shfl_xor(acc[p], o, 64);
+  }
+  if (store) {
+#pragma unroll
+    for (int p = 0; p < NQ; ++p) q[P0 + p] = acc[p];
+  }
+}
+
 template <int R>
 __device__ __forceinline__ void gram_work(const double* __restrict__ W64, const double* __restrict__ Gp,
                                           double* __restrict__ Qp, int nd, int ndd, const QItem it,
@@ -47,11 +99,9 @@ __device__ __forceinline__ void gram_work(const double* __restrict__ W64, const 
   const int ch = (int)(item & ((1 << lg) - 1));
   const int Ii = it.Ii;
   const bool valid = dd < it.D;
-  double acc[NP];
-#pragma unroll
-  for (int p = 0; p < NP; ++p) acc[p] = 0.0;
+  int im[MAXC];
+  double sdd = 1.0;
   if (valid) {
-    int im[MAXC];
     long long t = dd;
 #pragma unroll
     for (int c = MAXC - 1; c >= 0; --c) {
@@ -61,7 +111,6 @@ __device__ __forceinline__ void gram_work(const double* __restrict__ W64, const 
         t /= it.ddim[c];
       }
     }
-    double sdd = 1.0;
 #pragma unroll
     for (int q = 0; q < 3; ++q) {
       if (q < ndd) {
@@ -72,43 +121,21 @@ __device__ __forceinline__ void gram_work(const double* __restrict__ W64, const 
         sdd *= w * w;
       }
     }
-    const int lo = ch * it.CH, hi = min(Ii, lo + it.CH);
-    const double* Gik = Gp + it.gik;
-    constexpr int XU = R <= 6 ? 4 : 2;
-    for (int x0 = lo; x0 < hi; x0 += XU) {
-      double wv[XU][MAXC], g[XU][R];
+  } else {
 #pragma unroll
-      for (int u = 0; u < XU; ++u) {
-        const int x = min(x0 + u, hi - 1);
-#pragma unroll
-        for (int c = 0; c < MAXC; ++c) wv[u][c] = c < nd ? W64[eaddr(it.edi[c], im[c], x)] : 1.0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) g[u][r] = Gik[(long long)r * Ii + x];
-      }
-#pragma unroll
-      for (int u = 0; u < XU; ++u) {
-        const double live = (x0 + u < hi) ? 1.0 : 0.0;
-        double w = sdd * live;
-#pragma unroll
-        for (int c = 0; c < MAXC; ++c) w *= wv[u][c] * wv[u][c];
-        int p = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const double wr = w * g[u][r];
-#pragma unroll
-          for (int s2 = r; s2 < R; ++s2) acc[p++] += wr * g[u][s2];
-        }
-      }
-    }
+    for (int c = 0; c < MAXC; ++c) im[c] = 0;
   }
-  for (int o = 1; o < (1 << lg); o <<= 1) {
-#pragma unroll
-    for (int p = 0; p < NP; ++p) acc[p] += __shfl_xor(acc[p], o, 64);
-  }
-  if (valid && ch == 0) {
-    double* q = Qp + it.qoff + dd * NP;
-#pragma unroll
-    for (int p = 0; p < NP; ++p) q[p] = acc[p];
+  const int lo = ch * it.CH, hi = min(Ii, lo + it.CH);
+  const double* Gik = Gp + it.gik;
+  double* q = Qp + it.qoff + (valid ? dd : 0) * NP;
+  const bool store = valid && ch == 0;
+  if constexpr (R <= 4) {
+    gram_rows<R, 0, R, 4>(W64, Gik, q, nd, it, im, sdd, valid, lo, hi, lg, Ii, store);
+  } else if constexpr (R <= 6) {
+    gram_rows<R, 0, R, 2>(W64, Gik, q, nd, it, im, sdd, valid, lo, hi, lg, Ii, store);
+  } else {
+    gram_rows<R, 0, 2, 2>(W64, Gik, q, nd, it, im, sdd, valid, lo, hi, lg, Ii, store);
+    gram_rows<R, 2, R, 2>(W64, Gik, q, nd, it, im, sdd, valid, lo, hi, lg, Ii, store);
   }
 }
 
