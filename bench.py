@@ -99,6 +99,13 @@ def algorithmic_bytes(dims, esz, mask_frac):
     return nX, read, upd
 
 
+def contraction_bytes(n_con, n_fused, read, upd):
+    """Algorithmic bytes of n_con contraction launches of which n_fused carry
+    the X step: a fused launch reads X once for both, so it moves `upd`
+    bytes and the others `read`."""
+    return (n_con - n_fused) * read + n_fused * upd
+
+
 def cpu_baseline(name, seed, sweeps_req):
     """The FP64 oracle (single thread) on a bounded sample of the workload."""
     try:
@@ -361,7 +368,7 @@ def main():
     N = len(p.dims)
     n_con = per["contract"]["launches"]
     n_fused = max(0, args.steps - 1)
-    con_bytes = n_con * rd + n_fused * upd
+    con_bytes = contraction_bytes(n_con, n_fused, rd, upd)
     dominant = max(per, key=lambda k: per[k]["total_ms"])
     con_gbs = con_bytes / (per["contract"]["total_ms"] * 1e-3) / 1e9
     traffic = measured_traffic(args.workload, args.precision)

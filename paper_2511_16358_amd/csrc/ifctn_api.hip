@@ -157,11 +157,15 @@ struct ContractPlan {
 constexpr int kTargetBlocks = 1024;
 
 // tuning options (ifctn_set_option): < 0 = default
-std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1}, g_onelaunch{-1};
+std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1}, g_onelaunch{-1}, g_contract_jmax{-1};
 bool phased_onelaunch() { return g_onelaunch.load() > 0; }   // off by default: measured slower
 bool merge_gram() { return g_merge_gram.load() != 0; }
 long long contract_div() { long long v = g_contract_div.load(); return v > 0 ? v : 1280; }
 long long contract_emin() { long long v = g_contract_emin.load(); return v > 0 ? v : 2048; }
+// at most 16 indices of mode k per workgroup: more, shorter workgroups (each
+// runs its X passes as a chain of dependent loads); measured best on the
+// 256 x 256 x 31 workload and on order-4/5 served tensors
+long long contract_jmax() { long long v = g_contract_jmax.load(); return v > 0 ? v : 16; }
 
 constexpr size_t kMaxLds = 64 << 10;
 
@@ -247,7 +251,7 @@ ContractPlan plan_contract(const Geo& g, int k) {
     // at least 2048 entries: measured best on the 256 x 256 x 31 workload)
     const long long E = std::min<long long>(65536, std::max<long long>(contract_emin(), g.nX / contract_div()));
     long long jn = (a.kind == 1 && a.plfast) ? std::min<long long>({(long long)a.Ik, jcapf, 8})
-                                             : std::min<long long>(a.Ik, jcapf);
+                                             : std::min<long long>({(long long)a.Ik, jcapf, contract_jmax()});
     long long JT = cdiv(a.Ik, jn);
     jn = cdiv(a.Ik, JT);
     long long PPW = std::max<long long>(1, std::min<long long>(a.nplanes, E / std::max<long long>(1, jn * a.If)));
@@ -1231,6 +1235,10 @@ ifctn_status ifctn_set_option(const char* name, int64_t value) {
   }
   if (std::strcmp(name, "contract_emin") == 0) {
     g_contract_emin.store(value);
+    return IFCTN_OK;
+  }
+  if (std::strcmp(name, "contract_jmax") == 0) {
+    g_contract_jmax.store(value);
     return IFCTN_OK;
   }
   return fail(IFCTN_E_INVAL, "unknown option '%s'", name);
