@@ -250,7 +250,7 @@ ifctn_status ifctn_image_metrics(const void* X_dev, const void* ref_dev, int64_t
  *   instead of as extra workgroups of the contraction launch (default).
  *   "contract_div", "contract_emin": a contraction workgroup covers about
  *   max(contract_emin, nX / contract_div) tensor entries (defaults 1280 and
- *   2048; values <= 0 restore them).
+ *   4096; values <= 0 restore them).
  *   "contract_jmax": a contraction workgroup whose fibre or own mode is the
  *   contiguous one spans at most this many indices of mode k, and at most as
  *   many as eight accumulator slots per thread allow (default 16; values

@@ -161,7 +161,7 @@ std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1}
 bool phased_onelaunch() { return g_onelaunch.load() > 0; }   // off by default: measured slower
 bool merge_gram() { return g_merge_gram.load() != 0; }
 long long contract_div() { long long v = g_contract_div.load(); return v > 0 ? v : 1280; }
-long long contract_emin() { long long v = g_contract_emin.load(); return v > 0 ? v : 2048; }
+long long contract_emin() { long long v = g_contract_emin.load(); return v > 0 ? v : 4096; }
 // at most 16 indices of mode k per workgroup: more, shorter workgroups (each
 // runs its X passes as a chain of dependent loads); measured best on the
 // 256 x 256 x 31 workload and on order-4/5 served tensors
@@ -248,7 +248,8 @@ ContractPlan plan_contract(const Geo& g, int k) {
     const long long jcapf = std::max<long long>(1, (long long)NT * 8 / a.Rprod);   // <= 8 slots per thread
     // workgroups of a few thousand elements: enough work to amortise the
     // per-plane set-up, several hundred workgroups over the chip (nX / 1280,
-    // at least 2048 entries: measured best on the 256 x 256 x 31 workload)
+    // at least 4096 entries: measured best on the 256 x 256 x 31 workload
+    // and on order-4/5 served tensors)
     const long long E = std::min<long long>(65536, std::max<long long>(contract_emin(), g.nX / contract_div()));
     long long jn = (a.kind == 1 && a.plfast) ? std::min<long long>({(long long)a.Ik, jcapf, 8})
                                              : std::min<long long>({(long long)a.Ik, jcapf, contract_jmax()});
