@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--serve-slots", type=int, default=16)
     ap.add_argument("--serve-streams", type=int, default=16)
     ap.add_argument("--serve-round", type=int, default=10)
+    ap.add_argument("--serve-sequential", type=int, default=32,
+                    help="requests of the mix also run alone, one after another (0 = skip)")
     ap.add_argument("--no-tuning", action="store_true", help="skip the rank-grid tuning leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=0, help="oracle sweeps (0 = auto, ~10-30 s)")
@@ -227,6 +229,23 @@ def serve_mix(ifctn, torch, args):
             done[c["tag"]] = c
     wall = time.perf_counter() - t0
     srv.close()
+    # the first requests of the mix again, alone and one after another through
+    # ifctn_complete (same precision, refinement, t_max and eps): the rate
+    # without the server's overlap of jobs
+    seq = None
+    nseq = min(args.serve_sequential, len(specs))
+    if nseq > 0:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        seq_sweeps = 0
+        for sp, (O, M, G0) in zip(specs[:nseq], inputs[:nseq]):
+            _, st = ifctn.complete(O, M, G0, sp.dims, sp.ranks, W.SERVED["t_max"], eps=W.SERVED["eps"],
+                                   precision=prec, refine_sweeps=refine)
+            seq_sweeps += st["sweeps_done"]
+        torch.cuda.synchronize()
+        t_seq = time.perf_counter() - t1
+        seq = {"requests": nseq, "sweeps": int(seq_sweeps), "wall_s": round(t_seq, 3),
+               "sweeps_per_s": round(seq_sweeps / t_seq, 1)}
     bad = [c for c in done.values() if c["status"] != ifctn.IFCTN_OK]
     lat = np.array([c["t_done"] - c["t_submit"] for c in done.values()])
     queue = np.array([c["t_admit"] - c["t_submit"] for c in done.values()])
@@ -249,6 +268,9 @@ def serve_mix(ifctn, torch, args):
             "server": {"hbm_budget_gb": args.serve_budget_gb, "slots": args.serve_slots,
                        "streams": args.serve_streams, "sweeps_per_round": args.serve_round},
             "input_generation_s": round(t_gen, 2),
+            "sequential": seq,
+            "served_over_sequential": (round((sweeps / (last - first)) / seq["sweeps_per_s"], 3)
+                                       if seq else None),
             "mix": f"{len(specs)} requests, Poisson arrivals at 200/s, orders 3-5, modes 16-256 (<= 4,194,304 entries), "
                    "R in 2..6, sampling 5/10/30%, planted iFCTN N(0,1) unit max + N(0,0.01^2), "
                    "t_max 100, eps 1e-5"}

@@ -260,8 +260,14 @@ def complete(O, mask, G0, dims, ranks, t_max, eps=0.0, rho=0.1, precision=IFCTN_
     dims = tuple(int(d) for d in dims)
     params = make_params(dims, ranks, rho, 0.0, precision, refine_sweeps)
     dt = _dtype(precision)
-    Ot = torch.as_tensor(np.asarray(O)).to(device="cuda", dtype=dt).contiguous()
-    Mt = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to("cuda").contiguous()
+    if isinstance(O, torch.Tensor):
+        Ot = O.to(device="cuda", dtype=dt).contiguous()
+    else:
+        Ot = torch.as_tensor(np.asarray(O)).to(device="cuda", dtype=dt).contiguous()
+    if isinstance(mask, torch.Tensor):
+        Mt = mask.to(device="cuda", dtype=torch.uint8).contiguous()
+    else:
+        Mt = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to("cuda").contiguous()
     g0 = np.ascontiguousarray(workloads.pack(G0, dims, ranks) if isinstance(G0, dict) else G0,
                               dtype=np.float64)
     out = torch.empty(dims, dtype=dt, device="cuda")
