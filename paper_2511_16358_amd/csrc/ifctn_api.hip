@@ -169,13 +169,10 @@ long long contract_jmax() { long long v = g_contract_jmax.load(); return v > 0 ?
 
 constexpr size_t kMaxLds = 64 << 10;
 
-ContractPlan plan_contract(const Geo& g, int k) {
-  ContractPlan P;
-  ContractArgs& a = P.a;
-  std::memset(&a, 0, sizeof(a));
+// fibre mode f: the contiguous last mode when it is long enough, otherwise
+// the longest mode != k (the Kronecker accumulation costs Rprod / I_f per element)
+int preferred_fibre(const Geo& g, int k) {
   const int N = g.N;
-  // fibre mode f: the contiguous last mode when it is long enough, otherwise
-  // the longest mode != k (the Kronecker accumulation costs Rprod / I_f per element)
   int f = -1;
   if (k != N - 1 && g.dims[N - 1] >= 16) {
     f = N - 1;
@@ -183,6 +180,14 @@ ContractPlan plan_contract(const Geo& g, int k) {
     for (int m = 0; m < N; ++m)
       if (m != k && (f < 0 || g.dims[m] >= g.dims[f])) f = m;
   }
+  return f;
+}
+
+ContractPlan plan_contract_f(const Geo& g, int k, int f) {
+  ContractPlan P;
+  ContractArgs& a = P.a;
+  std::memset(&a, 0, sizeof(a));
+  const int N = g.N;
   a.k = k;
   a.f = f;
   a.Ik = g.dims[k];
@@ -273,11 +278,6 @@ ContractPlan plan_contract(const Geo& g, int k) {
     a.PPW = PPW;
     a.PB = (int)std::min<long long>(PPW, a.kind == 1 ? 64 : 32);
     a.fch = 1;
-    if (a.kind == 1) {
-      int fch = 1;
-      while (fch < 64 && a.If / (2 * fch) >= 4) fch *= 2;
-      a.fch = fch;
-    }
     // two or more c-modes: contract the last one first (staged accumulation)
     // when the batches and workgroups can hold whole groups of its planes
     a.stage = 0;
@@ -298,6 +298,22 @@ ContractPlan plan_contract(const Geo& g, int k) {
       }
     }
     while (a.PB > 1 && contract_smem_bytes(g.dtype, a) > kMaxLds) a.PB = std::max(1, a.PB * 3 / 4);
+    // a fibre too long for the LDS tables (fibre factor, per-plane scales):
+    // split it into chunks over workgroups, each with a partial slot of its
+    // own; chunks are re-balanced so that none is empty
+    {
+      long long fcs = cdiv(a.If, a.FS);
+      while (fcs > 1 && contract_smem_bytes(g.dtype, a) > kMaxLds) {
+        fcs = cdiv(fcs, 2);
+        a.FS = (int)cdiv(a.If, fcs);
+      }
+    }
+    if (a.kind == 1) {   // lanes per fibre row: at least 4 entries of the chunk each
+      const int fc = (a.If + a.FS - 1) / a.FS;
+      int fch = 1;
+      while (fch < 64 && fc / (2 * fch) >= 4) fch *= 2;
+      a.fch = fch;
+    }
     int ps = 1;
     const int units = a.stage ? a.PB / a.cdl : a.PB;   // what the split threads share: planes or groups
     while (ps < 16 && jn * a.Rprod * ps * 2 <= NT && units >= 2 * ps) ps *= 2;
@@ -395,7 +411,7 @@ bool plan_ok(const Geo& g, const ContractPlan& P, const char** why) {
   const ContractArgs& a = P.a;
   if ((long long)a.JT * a.jn < a.Ik || (long long)(a.JT - 1) * a.jn >= a.Ik) { *why = "j tiling"; return false; }
   if ((long long)a.S * a.PPW < a.nplanes || (long long)(a.S - 1) * a.PPW >= a.nplanes) { *why = "plane split"; return false; }
-  if (a.FS < 1 || (a.FS > 1 && a.kind != 2) || (long long)(a.FS - 1) * ((a.If + a.FS - 1) / a.FS) >= a.If) { *why = "fibre split"; return false; }
+  if (a.FS < 1 || (a.FS > 1 && a.kind == 0) || (long long)(a.FS - 1) * ((a.If + a.FS - 1) / a.FS) >= a.If) { *why = "fibre split"; return false; }
   if ((long long)a.nplanes * a.Ik * a.If != g.nX) { *why = "plane count"; return false; }
   if ((long long)a.jn * a.Rprod * a.psplit > (long long)P.spt * NT || P.spt > 32) { *why = "accumulator slots"; return false; }
   if (a.psplit > 1 && (long long)a.jn * a.Rprod * a.psplit > NT) { *why = "split slots"; return false; }
@@ -407,6 +423,28 @@ bool plan_ok(const Geo& g, const ContractPlan& P, const char** why) {
   if (P.smem > kMaxLds) { *why = "LDS size"; return false; }
   if (a.Rf > MAXR || a.Rc > 4096) { *why = "rank product"; return false; }
   return true;
+}
+
+// The preferred fibre mode's plan, or, when that one breaks an invariant (a
+// long fibre that only the generic layout could take, whose LDS tables would
+// not fit), the first valid plan over the other modes: the contiguous last
+// mode first, then by decreasing length.
+ContractPlan plan_contract(const Geo& g, int k) {
+  const int f0 = preferred_fibre(g, k);
+  ContractPlan P = plan_contract_f(g, k, f0);
+  const char* why = nullptr;
+  if (plan_ok(g, P, &why)) return P;
+  int order[MAXN], n = 0;
+  if (g.N - 1 != k && g.N - 1 != f0) order[n++] = g.N - 1;
+  for (int m = 0; m < g.N; ++m)
+    if (m != k && m != f0 && m != g.N - 1) order[n++] = m;
+  std::stable_sort(order + (n > 0 && order[0] == g.N - 1 ? 1 : 0), order + n,
+                   [&](int x, int y) { return g.dims[x] > g.dims[y]; });
+  for (int q = 0; q < n; ++q) {
+    ContractPlan Q = plan_contract_f(g, k, order[q]);
+    if (plan_ok(g, Q, &why)) return Q;
+  }
+  return P;   // the caller reports why it is invalid
 }
 
 QArgs plan_q(const Geo& g, int k, long long* qsize) {
@@ -525,8 +563,19 @@ long long phased_min() {
 bool use_phased(const Geo& g, const QArgs& Q, int k) {
   long long m = 0;
   for (int t = 0; t < g.N - 1; ++t) m = std::max(m, Q.it[t].D * (long long)(Q.it[t].R * (Q.it[t].R + 1) / 2));
-  (void)k;
-  return m >= phased_min();
+  if (m >= phased_min()) return true;
+  // the per-column kernel keeps the column's edge rows of every other mode in
+  // LDS; when a long mode makes them too large, the phased form (which reads
+  // them from HBM) takes the block
+  SolveArgs sa;
+  std::memset(&sa, 0, sizeof(sa));
+  sa.Rprod = 1;
+  for (int q = 0; q < g.N; ++q)
+    if (q != k) {
+      sa.Rprod *= g.R[k][q];
+      sa.rowtot += (int)g.dims[q];
+    }
+  return solve_smem_bytes(sa) > kMaxLds;
 }
 
 int hp_width(int Ik) {

@@ -571,17 +571,21 @@ struct FLayout {
   size_t pbase, pidx, acoef, scc, scf, t0, w0f, gf, T, tpart, red, T2, gl, total;
 };
 
+// fibre entries per workgroup: the fibre range is split into FS chunks
+__host__ __device__ inline int fibre_chunk(const ContractArgs& a) { return a.FS == 1 ? a.If : (a.If + a.FS - 1) / a.FS; }
+
 __host__ __device__ inline FLayout flayout(int tcsz, const ContractArgs& a) {
   FLayout L;
   size_t o = 0;
+  const size_t fcs = (size_t)fibre_chunk(a);
   L.pbase = o; o = al16(o + (size_t)a.PB * 8);
   L.pidx = o;  o = al16(o + (size_t)a.PB * MAXC * 4);
   L.acoef = o; o = al16(o + (size_t)a.PB * a.Rc * 8);
   L.scc = o;   o = al16(o + (size_t)a.PB * tcsz);
-  L.scf = o;   o = al16(o + (size_t)a.PB * a.If * tcsz);
+  L.scf = o;   o = al16(o + (size_t)a.PB * fcs * tcsz);
   L.t0 = o;    o = al16(o + (size_t)a.PB * a.jn * tcsz);
-  L.w0f = o;   o = al16(o + (size_t)(a.k == 0 ? a.jn * a.If : 0) * tcsz);
-  L.gf = o;    o = al16(o + (size_t)a.If * MAXR * tcsz);      // zero-padded to MAXR ranks
+  L.w0f = o;   o = al16(o + (size_t)(a.k == 0 ? a.jn * fcs : 0) * tcsz);
+  L.gf = o;    o = al16(o + fcs * MAXR * tcsz);               // zero-padded to MAXR ranks
   L.T = o;     o = al16(o + std::max((size_t)a.PB * a.jn * a.Rf * tcsz, (size_t)NT * 8));
   L.tpart = o; o = al16(o + (a.kind == 2 ? (size_t)NT * a.Rf * tcsz : 0));
   L.red = o;   o = al16(o + 4 * 3 * 8);
@@ -597,13 +601,13 @@ __host__ __device__ inline FLayout flayout(int tcsz, const ContractArgs& a) {
 template <typename TC, int NC>
 __device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0, int np, int jcnt, int j0,
                                             long long* pbase, int* pidx, TC* sccl, TC* scf, double* acoef,
-                                            TC* t0, bool con, bool upd) {
+                                            TC* t0, bool con, bool upd, int flo, int fcn, int fcs) {
   const TC* __restrict__ Wc = (const TC*)a.Wc;
-  const int tid = threadIdx.x, If = a.If, Rc = a.Rc, jn = a.jn;
+  const int tid = threadIdx.x, Rc = a.Rc, jn = a.jn;
   FDiv fcd[NC > 0 ? NC : 1];
 #pragma unroll
   for (int c = 0; c < NC; ++c) fcd[c] = mkdiv(a.cdim[c]);
-  const FDiv fIf = mkdiv(If);
+  const FDiv fIf = mkdiv(fcn);
   for (int e = tid; e < np; e += NT) {
     long long base = 0;
     int p = (int)(pb0 + e);          // plane index (< 2^31: the plane count is checked on the host)
@@ -624,17 +628,22 @@ __device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0
     for (int c = 0; c < NC; ++c) pidx[e * MAXC + c] = ic[c];
   }
   __syncthreads();
+  // scf(pl, f) for the fibre chunk: row pl at pl * fcs
   for_batched<4>(
-      np * If,
+      np * fcn,
       [&](int e) {
         int ff;
         const int pl = fdivmod(e, fIf, &ff);
         TC v = sccl[pl];
 #pragma unroll
-        for (int c = 0; c < NC; ++c) v *= Wc[eaddr(a.ecf[c], pidx[pl * MAXC + c], ff)];
+        for (int c = 0; c < NC; ++c) v *= Wc[eaddr(a.ecf[c], pidx[pl * MAXC + c], flo + ff)];
         return v;
       },
-      [&](int e, TC v) { scf[e] = v; });
+      [&](int e, TC v) {
+        int ff = e, pl = 0;
+        if (fcn != fcs) pl = fdivmod(e, fIf, &ff);   // a short last chunk: rows keep stride fcs
+        scf[pl * fcs + ff] = v;
+      });
   if (con && a.stage) {
     // per group of cdl planes: product over the c-modes but the last
     const int ng = np / a.cdl, Rc2 = a.Rc2;
@@ -693,13 +702,13 @@ __device__ __forceinline__ void plane_setup(const ContractArgs& a, long long pb0
 
 // G_{f,k} as gf[f][r] zero-padded to MAXR ranks (unconditional FMAs later)
 template <typename TC>
-__device__ __forceinline__ void load_gf(const ContractArgs& a, TC* gf) {
+__device__ __forceinline__ void load_gf(const ContractArgs& a, TC* gf, int flo, int fcn) {
   const int If = a.If, Rf = a.Rf;
   for_batched<4>(
-      If * MAXR,
+      fcn * MAXR,
       [&](int e) {
         const int ff = e / MAXR, r = e - ff * MAXR;
-        return r < Rf ? a.G[a.gfoff + (long long)r * If + ff] : 0.0;
+        return r < Rf ? a.G[a.gfoff + (long long)r * If + flo + ff] : 0.0;
       },
       [&](int e, double v) { gf[e] = (TC)v; });
 }
@@ -874,37 +883,44 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
   double* red = (double*)(smem + Ly.red);
 
   const int tid = threadIdx.x, bid = blockIdx.x - a.gblocks;   // contraction workgroup index
-  const int jt = bid % a.JT, sp = bid / a.JT;
+  const int jt = bid % a.JT, spf = bid / a.JT;          // partial index = plane split * FS + fibre split
+  const int sp = a.FS == 1 ? spf : spf / a.FS, fs = spf - sp * a.FS;
   const int j0 = jt * a.jn, jcnt = min(a.jn, a.Ik - j0);
   const long long p_begin = (long long)sp * a.PPW, p_end = min(a.nplanes, p_begin + a.PPW);
   const TC* __restrict__ Wc = (const TC*)a.Wc;
   TX* __restrict__ X = (TX*)a.X;
-  const int If = a.If, Rf = a.Rf, jn = a.jn;
+  const int Rf = a.Rf, jn = a.jn;
+  // this workgroup's fibre chunk [flo, fhi); the fibre tables hold it with row stride fcs
+  const int fcs = fibre_chunk(a), flo = fs * fcs, fhi = min(a.If, flo + fcs), fcn = fhi - flo;
 
   Slots<SPT> sl;
   double* T2 = (double*)(smem + Ly.T2);
   double* gl = (double*)(smem + Ly.gl);
   if (CON) {
     sl.template init<NC>(a, jcnt);
-    load_gf<TC>(a, gf);
+    load_gf<TC>(a, gf, flo, fcn);
     if (NC >= 2 && a.stage) load_gl(a, gl);
   }
   if (UPD)
     for_batched<4>(
-        jcnt * If,
+        jcnt * fcn,
         [&](int e) {
           int ff;
-          const int jl = fdivmod(e, mkdiv(If), &ff);
-          return Wc[eaddr(a.e0f, j0 + jl, ff)];
+          const int jl = fdivmod(e, mkdiv(fcn), &ff);
+          return Wc[eaddr(a.e0f, j0 + jl, flo + ff)];
         },
-        [&](int e, TC v) { w0f[e] = v; });
+        [&](int e, TC v) {
+          int ff = e, jl = 0;
+          if (fcn != fcs) jl = fdivmod(e, mkdiv(fcn), &ff);
+          w0f[jl * fcs + ff] = v;
+        });
   double dx2 = 0.0, x2 = 0.0, f2 = 0.0;
   const TC rx = (TC)a.rho_x, inv1 = (TC)1 / ((TC)1 + rx);
-  const int fch = a.fch, rpp = NT / fch, chunk = (If + fch - 1) / fch, ch = tid & (fch - 1);
+  const int fch = a.fch, rpp = NT / fch, chunk = (fcn + fch - 1) / fch, ch = tid & (fch - 1);
 
   for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
     const int np = (int)min((long long)a.PB, p_end - pb0);
-    plane_setup<TC, NC>(a, pb0, np, jcnt, j0, pbase, pidx, sccl, scf, acoef, t0, CON, UPD);
+    plane_setup<TC, NC>(a, pb0, np, jcnt, j0, pbase, pidx, sccl, scf, acoef, t0, CON, UPD, flo, fcn, fcs);
     const int rows = np * jcnt;
     const int passes = (rows + rpp - 1) / rpp;
     const FDiv frow = mkdiv(a.plfast ? np : jcnt);
@@ -920,10 +936,11 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
       const int pl = a.plfast ? rq : rd;
       const int jl = a.plfast ? rd : rq;
       const long long base = pbase[pl] + (long long)(j0 + jl) * a.stride_k;
-      const TC* sr = scf + pl * If;
-      const TC* wr = w0f + jl * If;
+      // chunk-relative fibre tables: entry f of the tensor sits at f - flo
+      // of its row (the offsets fold the chunk start; every index is >= 0)
+      const int sro = pl * fcs - flo, wro = jl * fcs - flo, gfo = -flo * MAXR;
       const TC tt = UPD ? t0[pl * jn + jl] : (TC)0;
-      const int lo = ch * chunk, hi = rok ? min(If, lo + chunk) : lo;
+      const int lo = flo + ch * chunk, hi = rok ? min(fhi, lo + chunk) : lo;
       for (int f0 = lo; f0 < hi; f0 += 4) {
         TX xv[4];
         uint32_t mw[4];
@@ -938,10 +955,10 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
           const int ff = min(f0 + u, hi - 1);
           const bool live = f0 + u < hi;
           TC x = (TC)xv[u];
-          const TC sk = sr[ff];
+          const TC sk = scf[sro + ff];
           if (UPD) {
             const long long L = base + ff;
-            const TC xh = sk * tt * wr[ff];
+            const TC xh = sk * tt * w0f[wro + ff];
             const bool obs = (mw[u] >> (L & 31)) & 1u;
             const TC xn = obs ? x : (TC)(TX)((xh + rx * x) * inv1);   // as stored
             if (live && !obs) X[L] = (TX)xn;
@@ -955,7 +972,7 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
           }
           if (CON) {
             const TC y = live ? x * sk : (TC)0;
-            const TC* g = gf + ff * MAXR;
+            const TC* g = gf + (gfo + ff * MAXR);
 #pragma unroll
             for (int r = 0; r < MAXR; ++r) t[r] += y * g[r];
           }
@@ -982,7 +999,7 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
     }
     __syncthreads();
   }
-  if (CON) sl.template write<NC>(a, (double*)(smem + Ly.T), sp, j0);
+  if (CON) sl.template write<NC>(a, (double*)(smem + Ly.T), spf, j0);
   if (UPD) block_norms(dx2, x2, f2, red, a.normpart + (long long)bid * 3);
 }
 
@@ -1013,19 +1030,19 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
   const long long p_begin = (long long)sp * a.PPW, p_end = min(a.nplanes, p_begin + a.PPW);
   const TX* __restrict__ X = (const TX*)a.X;
   const int If = a.If, Rf = a.Rf, jn = a.jn;
-  const int fcs = (If + a.FS - 1) / a.FS, flo = fs * fcs, fhi = min(If, flo + fcs);
+  const int fcs = fibre_chunk(a), flo = fs * fcs, fhi = min(If, flo + fcs), fcn = fhi - flo;
   const long long sf = a.stride_f;
 
   Slots<SPT> sl;
   double* T2 = (double*)(smem + Ly.T2);
   double* gl = (double*)(smem + Ly.gl);
   sl.template init<NC>(a, jcnt);
-  load_gf<TC>(a, gf);
+  load_gf<TC>(a, gf, flo, fcn);
   if (NC >= 2 && a.stage) load_gl(a, gl);
 
   for (long long pb0 = p_begin; pb0 < p_end; pb0 += a.PB) {
     const int np = (int)min((long long)a.PB, p_end - pb0);
-    plane_setup<TC, NC>(a, pb0, np, jcnt, j0, pbase, pidx, sccl, scf, acoef, t0, true, false);
+    plane_setup<TC, NC>(a, pb0, np, jcnt, j0, pbase, pidx, sccl, scf, acoef, t0, true, false, flo, fcn, fcs);
     const int NI = np * jcnt;                     // (plane, j) columns of this batch
     const int fg = NI >= NT ? 1 : NT / NI;        // fibre groups within the workgroup
     const int fchunk = (fhi - flo + fg - 1) / fg;
@@ -1040,7 +1057,7 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
       for (int r = 0; r < MAXR; ++r) t[r] = (TC)0;
       int jl;
       const int pl = fdivmod(itc, mkdiv(jcnt), &jl);
-      const TC* sr = scf + pl * If;
+      const int sro = pl * fcs - flo, gfo = -flo * MAXR;   // chunk-relative, as in the rows kernel
       const long long base = pbase[pl] + j0 + jl;
       const int lo = flo + (ok ? g : 0) * fchunk, hi = ok ? min(fhi, lo + fchunk) : lo;
       for (int f0 = lo; f0 < hi; f0 += 4) {
@@ -1050,8 +1067,8 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int ff = min(f0 + u, hi - 1);
-          const TC y = (f0 + u < hi) ? (TC)xv[u] * sr[ff] : (TC)0;
-          const TC* gg = gf + ff * MAXR;
+          const TC y = (f0 + u < hi) ? (TC)xv[u] * scf[sro + ff] : (TC)0;
+          const TC* gg = gf + (gfo + ff * MAXR);
 #pragma unroll
           for (int r = 0; r < MAXR; ++r) t[r] += y * gg[r];
         }

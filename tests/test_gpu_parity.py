@@ -339,6 +339,42 @@ def test_fully_observed_fixed_point():
     job.close()
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_no_observed_entry(prec):
+    """An empty mask: X^0 = 0, so the first relative change is infinite on
+    both sides, and the iteration then follows the factors alone."""
+    import dataclasses
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem((9, 7, 6), W.uniform_ranks(3, 2), seed=21, keep=0.5)
+    p = dataclasses.replace(p, O=np.zeros(p.dims, dtype=np.float32), mask=np.zeros(p.dims, dtype=np.uint8))
+    precision = ifctn.IFCTN_FP64 if prec == "fp64" else ifctn.IFCTN_FP32
+    r = run_both(p, 3, precision)
+    assert r["gs"][0]["rel_change"] == float("inf") and r["os"][0]["rel_change"] == float("inf")
+    tol = 1e-10 if prec == "fp64" else 2e-5
+    assert relerr(r["Xg"], r["Xo"]) < tol
+    for key in r["Go"]:
+        assert relerr(r["Gg"][key], r["Go"][key]) < 10 * tol, key
+
+
+LONG = [(40000, 3), (3, 40000), (20000, 4, 3), (5, 3, 30000)]
+
+
+@pytest.mark.parametrize("dims", LONG, ids=["x".join(map(str, d)) for d in LONG])
+def test_long_fibre(dims):
+    """A mode too long for a fibre's LDS tables: the fibre is split into
+    chunks over workgroups (each with a partial slot), or another mode serves
+    as fibre.  Two FP64 sweeps against the oracle (the second carries the
+    fused X step on the chunked fibre) and two FP32 sweeps."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem(dims, W.uniform_ranks(len(dims), 2), seed=22, keep=0.3)
+    r = run_both(p, 2, ifctn.IFCTN_FP64)
+    assert relerr(r["Xg"], r["Xo"]) < 1e-10
+    for key in r["Go"]:
+        assert relerr(r["Gg"][key], r["Go"][key]) < 1e-9, key
+    r = run_both(p, 2, ifctn.IFCTN_FP32)
+    assert relerr(r["Xg"], r["Xo"]) < 2e-5
+
+
 # --------------------------------------------------------------------------
 # full-size workloads in the benchmark's launch configuration
 # --------------------------------------------------------------------------

@@ -20,6 +20,8 @@ SHAPES = [
     ((7, 13, 5), 3), ((9, 11), 4), ((5, 6, 7, 3), 2), ((4, 3, 5, 2, 3), 2), ((1, 1, 1), 1),
     ((3, 1, 4), 2), ((17, 33, 9), 8), ((144, 176, 50, 3), 5), ((16, 16, 16, 16, 16), 6),
     ((45, 44, 46, 43), 4), ((20, 19, 21, 18, 22), 6), ((4, 4, 4, 4, 4), 8),
+    # long fibres: split into chunks over workgroups, or another fibre mode
+    ((40000, 3), 2), ((3, 40000), 2), ((20000, 4, 3), 2), ((5, 3, 30000), 2),
 ]
 
 PLAN_RE = re.compile(r"\[ifctn plan\] (.*?) \|")
@@ -160,9 +162,10 @@ def simulate_fast(dims, plan, kind, FS, strides, cm, cdim, slot_to_col):
                 rows = np.arange(npl * jcnt)
                 pl = rows % npl if plfast else rows // jcnt
                 jl = rows // npl if plfast else rows % jcnt
-                chunk = -(-If // fch)
-                assert chunk * fch >= If
-                ff = np.arange(If)
+                chunk = -(-(fhi - flo) // fch)             # fibre lanes share the chunk
+                assert chunk * fch >= fhi - flo
+                ff = np.arange(flo, fhi)
+                assert (ff - flo).max() < fcs                # chunk-relative LDS tables
                 L = (base[pl] + (j0 + jl) * strides[k])[:, None] + ff[None, :]
             else:
                 NI = npl * jcnt
