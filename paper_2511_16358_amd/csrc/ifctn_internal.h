@@ -174,9 +174,9 @@ struct SolveArgs {
 // then k_solve_col reduces the partials of column j in a fixed order, forms
 // b_j, solves and refreshes row j of W_{k,i}.  The Gauss-Seidel order over i
 // is kept by launching the sub-blocks one after another.
-constexpr int HP_JW = 32;     // max columns per k_hpart workgroup (power of two)
+constexpr int HP_JW = 16;     // max columns per k_hpart workgroup (power of two)
 constexpr int HS_JW = 4;      // columns per workgroup of the one-launch form (one wave each)
-constexpr int HP_DC = 112;    // d per k_hpart workgroup
+constexpr int HP_DC = 28;     // d per k_hpart workgroup (many short workgroups: measured best on the served mix)
 
 struct PhaseArgs {
   SubBlock B;

@@ -394,11 +394,17 @@ __global__ __launch_bounds__(NT) void k_urow(SolveArgs a, double* __restrict__ U
 }
 
 // Partial H_j(p) = sum_{d in range} w_j(d) Q(d, p) for a tile of columns.
+// LDS of k_hpart: the weight and Gram-entry tiles, later reused for the
+// cross-wave reduction of the partial sums
+constexpr int HP_TILES = HP_JW * HP_DC + HP_DC * MAXP;
+constexpr int HP_RED = (NT / 64) * HP_JW * MAXP;
+constexpr int HP_SM = HP_TILES > HP_RED ? HP_TILES : HP_RED;
+
 template <int R>
 __global__ __launch_bounds__(NT) void k_hpart(PhaseArgs a) {
   if (a.stop && *a.stop) return;
   constexpr int NP = R * (R + 1) / 2;
-  __shared__ double sm[HP_JW * HP_DC + HP_DC * MAXP];
+  __shared__ double sm[HP_SM];
   double* wL = sm;                       // [jcnt][dn] weights
   double* qL = sm + HP_JW * HP_DC;       // [dn][NP] Gram weight entries
   const int tid = threadIdx.x;
@@ -578,6 +584,7 @@ __global__ __launch_bounds__(NT) void k_hsolve(PhaseArgs a) {
   constexpr int NP = R * (R + 1) / 2;
   constexpr int NW = NT / 64;
   __shared__ double sm[HS_JW * HP_DC + HP_DC * MAXP];
+  static_assert(HS_JW * HP_DC + HP_DC * MAXP >= (NT / 64) * HS_JW * MAXP, "reduction buffer");
   __shared__ double fH[NW][64], fB[NW][64], Hs[NW][MAXP], bs[NW][MAXR], gold[NW][MAXR], gnew[NW][MAXR];
   __shared__ int last;
   const int tid = threadIdx.x, wv = tid >> 6, lane = tid & 63;
