@@ -356,7 +356,7 @@ def test_no_observed_entry(prec):
         assert relerr(r["Gg"][key], r["Go"][key]) < 10 * tol, key
 
 
-LONG = [(40000, 3), (3, 40000), (20000, 4, 3), (5, 3, 30000)]
+LONG = [(40000, 3), (3, 40000), (20000, 4, 3), (5, 3, 30000), (3, 4, 5, 3000)]
 
 
 @pytest.mark.parametrize("dims", LONG, ids=["x".join(map(str, d)) for d in LONG])

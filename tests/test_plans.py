@@ -21,7 +21,7 @@ SHAPES = [
     ((3, 1, 4), 2), ((17, 33, 9), 8), ((144, 176, 50, 3), 5), ((16, 16, 16, 16, 16), 6),
     ((45, 44, 46, 43), 4), ((20, 19, 21, 18, 22), 6), ((4, 4, 4, 4, 4), 8),
     # long fibres: split into chunks over workgroups, or another fibre mode
-    ((40000, 3), 2), ((3, 40000), 2), ((20000, 4, 3), 2), ((5, 3, 30000), 2),
+    ((40000, 3), 2), ((3, 40000), 2), ((20000, 4, 3), 2), ((5, 3, 30000), 2), ((3, 4, 5, 3000), 2),
 ]
 
 PLAN_RE = re.compile(r"\[ifctn plan\] (.*?) \|")
