@@ -861,6 +861,19 @@ __device__ __forceinline__ void block_norms(double dx2, double x2, double f2, do
   }
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn (launch index mod 8), each
+// XCD with its own L2. Logical index L = (A mod 8) * q + A / 8 over the first
+// 8q launch indices (identity after them) puts logical neighbours -- j-tiles
+// that share cache lines of X, consecutive plane ranges -- on the same XCD.
+// A bijection on [0, total), so every logical workgroup runs exactly once.
+// Applied to the contraction workgroups only: the Gram workgroups keep the
+// first launch indices, spread over all XCDs (grouped on one XCD they would
+// become the launch's critical path).
+__device__ __forceinline__ int xcd_local(int A, int total) {
+  const int q = total >> 3;
+  return A < (q << 3) ? (A & 7) * q + (A >> 3) : A;
+}
+
 // rows variant (fibre mode contiguous) ---------------------------------------
 template <typename TX, typename TC, int NC, bool UPD, bool CON, int SPT>
 __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
@@ -882,7 +895,8 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
   TC* Tl = (TC*)(smem + Ly.T);
   double* red = (double*)(smem + Ly.red);
 
-  const int tid = threadIdx.x, bid = blockIdx.x - a.gblocks;   // contraction workgroup index
+  // contraction workgroup index, XCD-local among the contraction workgroups
+  const int tid = threadIdx.x, bid = xcd_local((int)blockIdx.x - a.gblocks, (int)gridDim.x - a.gblocks);
   const int jt = bid % a.JT, spf = bid / a.JT;          // partial index = plane split * FS + fibre split
   const int sp = a.FS == 1 ? spf : spf / a.FS, fs = spf - sp * a.FS;
   const int j0 = jt * a.jn, jcnt = min(a.jn, a.Ik - j0);
@@ -1023,7 +1037,8 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
   TC* Tl = (TC*)(smem + Ly.T);
   TC* tpart = (TC*)(smem + Ly.tpart);
 
-  const int tid = threadIdx.x, bid = blockIdx.x - a.gblocks;   // contraction workgroup index
+  // contraction workgroup index, XCD-local among the contraction workgroups
+  const int tid = threadIdx.x, bid = xcd_local((int)blockIdx.x - a.gblocks, (int)gridDim.x - a.gblocks);
   const int jt = bid % a.JT, spf = bid / a.JT;          // partial index = plane split * FS + fibre split
   const int sp = spf / a.FS, fs = spf - sp * a.FS;
   const int j0 = jt * a.jn, jcnt = min(a.jn, a.Ik - j0);
