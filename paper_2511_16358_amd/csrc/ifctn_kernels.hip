@@ -228,7 +228,7 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
   double* gnew = gold + MAXR;
 
   const int tid = threadIdx.x;
-  const int j = blockIdx.x;
+  const int j = xcd_local((int)blockIdx.x, (int)gridDim.x);   // neighbouring columns on one XCD
   const int Ik = a.Ik;
   double* G = a.G;
   TC* Wc = (TC*)a.Wc;
