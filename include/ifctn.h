@@ -253,7 +253,7 @@ ifctn_status ifctn_image_metrics(const void* X_dev, const void* ref_dev, int64_t
  *   4096; values <= 0 restore them).
  *   "contract_jmax": a contraction workgroup whose fibre or own mode is the
  *   contiguous one spans at most this many indices of mode k, and at most as
- *   many as eight accumulator slots per thread allow (default 16; values
+ *   many as eight accumulator slots per thread allow (default 8; values
  *   <= 0 restore it).
  * Unknown names: IFCTN_E_INVAL. */
 ifctn_status ifctn_set_option(const char* name, int64_t value);

@@ -162,10 +162,11 @@ bool phased_onelaunch() { return g_onelaunch.load() > 0; }   // off by default: 
 bool merge_gram() { return g_merge_gram.load() != 0; }
 long long contract_div() { long long v = g_contract_div.load(); return v > 0 ? v : 1280; }
 long long contract_emin() { long long v = g_contract_emin.load(); return v > 0 ? v : 4096; }
-// at most 16 indices of mode k per workgroup: more, shorter workgroups (each
-// runs its X passes as a chain of dependent loads); measured best on the
+// at most 8 indices of mode k per workgroup: more, shorter workgroups (each
+// runs its X passes as a chain of dependent loads; with XCD-local numbering
+// neighbouring tiles share their XCD's L2); measured best on the
 // 256 x 256 x 31 workload and on order-4/5 served tensors
-long long contract_jmax() { long long v = g_contract_jmax.load(); return v > 0 ? v : 16; }
+long long contract_jmax() { long long v = g_contract_jmax.load(); return v > 0 ? v : 8; }
 
 constexpr size_t kMaxLds = 64 << 10;
 
