@@ -42,6 +42,7 @@ extern "C" {
 
 #define IFCTN_MAX_ORDER 5 /* tensor order N: 2..5 */
 #define IFCTN_MAX_RANK 8  /* every R[a][b] in 1..8 */
+#define IFCTN_MAX_ENTRIES 2147483647LL /* prod(dims) above this: IFCTN_E_UNSUPPORTED */
 
 typedef enum {
   IFCTN_OK = 0,

@@ -167,12 +167,6 @@ def update_x(X, Xhat, O, mask, rho_x):
     return np.where(m, O, (Xhat + rho_x * X) / (1.0 + rho_x))
 
 
-def objective(X, G, dims):
-    """f(G, X) = 1/2 ||X - iFCTN(G)||_F^2 (F = f on feasible iterates)."""
-    d = X - reconstruct(G, dims)
-    return 0.5 * float(np.sum(d * d))
-
-
 def rse(X_true, X):
     """Relative error ||X_true - X||_F / ||X_true||_F (Sec. 5; reading: the
     denominator is the ground truth, as the Observed rows of Table 5 imply)."""

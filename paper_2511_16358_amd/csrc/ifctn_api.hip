@@ -64,6 +64,8 @@ struct Geo {
   long long nW = 0;
 };
 
+constexpr long long kMaxEntries = IFCTN_MAX_ENTRIES;
+
 ifctn_status make_geo(const ifctn_params* p, Geo* g) {
   if (!p) return fail(IFCTN_E_INVAL, "params is NULL");
   const int N = p->order;
@@ -83,6 +85,10 @@ ifctn_status make_geo(const ifctn_params* p, Geo* g) {
     nX *= p->dims[m];
     g->dims[m] = (int)p->dims[m];
   }
+  // the streaming kernels run one work-item per entry on a 1-D grid, whose
+  // work-item count is a 32-bit quantity
+  if (nX > kMaxEntries)
+    return fail(IFCTN_E_UNSUPPORTED, "tensor has %lld entries; at most %lld are supported", nX, kMaxEntries);
   g->nX = nX;
   long long st = 1;
   for (int m = N - 1; m >= 0; --m) {
@@ -158,15 +164,47 @@ constexpr int kTargetBlocks = 1024;
 
 // tuning options (ifctn_set_option): < 0 = default
 std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1}, g_onelaunch{-1}, g_contract_jmax{-1};
-bool phased_onelaunch() { return g_onelaunch.load() > 0; }   // off by default: measured slower
-bool merge_gram() { return g_merge_gram.load() != 0; }
-long long contract_div() { long long v = g_contract_div.load(); return v > 0 ? v : 1280; }
-long long contract_emin() { long long v = g_contract_emin.load(); return v > 0 ? v : 4096; }
-// at most 8 indices of mode k per workgroup: more, shorter workgroups (each
-// runs its X passes as a chain of dependent loads; with XCD-local numbering
-// neighbouring tiles share their XCD's L2); measured best on the
-// 256 x 256 x 31 workload and on order-4/5 served tensors
-long long contract_jmax() { long long v = g_contract_jmax.load(); return v > 0 ? v : 8; }
+// A factor block takes the phased form when one of its Gram weight sets is
+// large: the one-workgroup-per-column kernel would stream all of Q_{k,i}
+// through each of only I_k workgroups.
+constexpr long long kPhasedMinDefault = 16384;
+std::atomic<long long> g_phased_min{-1};
+
+}  // namespace
+
+namespace ifctn {
+// The options as they stand now; a job is planned with one snapshot from
+// sizing to creation (a server takes it at submit).
+PlanOpts current_opts() {
+  PlanOpts o;
+  long long v;
+  v = g_phased_min.load();
+  o.phased_min = v >= 0 ? v : kPhasedMinDefault;
+  o.onelaunch = g_onelaunch.load() > 0;                  // off by default: measured slower
+  o.merge_gram = g_merge_gram.load() != 0;
+  v = g_contract_div.load();
+  o.contract_div = v > 0 ? v : 1280;
+  v = g_contract_emin.load();
+  o.contract_emin = v > 0 ? v : 4096;
+  // at most 8 indices of mode k per workgroup: more, shorter workgroups (each
+  // runs its X passes as a chain of dependent loads; with XCD-local numbering
+  // neighbouring tiles share their XCD's L2); measured best on the
+  // 256 x 256 x 31 workload and on order-4/5 served tensors
+  v = g_contract_jmax.load();
+  o.contract_jmax = v > 0 ? v : 8;
+  return o;
+}
+std::atomic<long long> g_inject_admit{0};
+
+bool take_injected_admit_failure() {
+  long long v = g_inject_admit.load();
+  while (v > 0)
+    if (g_inject_admit.compare_exchange_weak(v, v - 1)) return true;
+  return false;
+}
+}  // namespace ifctn
+
+namespace {
 
 constexpr size_t kMaxLds = 64 << 10;
 
@@ -184,7 +222,7 @@ int preferred_fibre(const Geo& g, int k) {
   return f;
 }
 
-ContractPlan plan_contract_f(const Geo& g, int k, int f) {
+ContractPlan plan_contract_f(const Geo& g, int k, int f, const PlanOpts& o) {
   ContractPlan P;
   ContractArgs& a = P.a;
   std::memset(&a, 0, sizeof(a));
@@ -256,9 +294,9 @@ ContractPlan plan_contract_f(const Geo& g, int k, int f) {
     // per-plane set-up, several hundred workgroups over the chip (nX / 1280,
     // at least 4096 entries: measured best on the 256 x 256 x 31 workload
     // and on order-4/5 served tensors)
-    const long long E = std::min<long long>(65536, std::max<long long>(contract_emin(), g.nX / contract_div()));
+    const long long E = std::min<long long>(65536, std::max<long long>(o.contract_emin, g.nX / o.contract_div));
     long long jn = (a.kind == 1 && a.plfast) ? std::min<long long>({(long long)a.Ik, jcapf, 8})
-                                             : std::min<long long>({(long long)a.Ik, jcapf, contract_jmax()});
+                                             : std::min<long long>({(long long)a.Ik, jcapf, o.contract_jmax});
     long long JT = cdiv(a.Ik, jn);
     jn = cdiv(a.Ik, JT);
     long long PPW = std::max<long long>(1, std::min<long long>(a.nplanes, E / std::max<long long>(1, jn * a.If)));
@@ -430,9 +468,9 @@ bool plan_ok(const Geo& g, const ContractPlan& P, const char** why) {
 // long fibre that only the generic layout could take, whose LDS tables would
 // not fit), the first valid plan over the other modes: the contiguous last
 // mode first, then by decreasing length.
-ContractPlan plan_contract(const Geo& g, int k) {
+ContractPlan plan_contract(const Geo& g, int k, const PlanOpts& o) {
   const int f0 = preferred_fibre(g, k);
-  ContractPlan P = plan_contract_f(g, k, f0);
+  ContractPlan P = plan_contract_f(g, k, f0, o);
   const char* why = nullptr;
   if (plan_ok(g, P, &why)) return P;
   int order[MAXN], n = 0;
@@ -442,7 +480,7 @@ ContractPlan plan_contract(const Geo& g, int k) {
   std::stable_sort(order + (n > 0 && order[0] == g.N - 1 ? 1 : 0), order + n,
                    [&](int x, int y) { return g.dims[x] > g.dims[y]; });
   for (int q = 0; q < n; ++q) {
-    ContractPlan Q = plan_contract_f(g, k, order[q]);
+    ContractPlan Q = plan_contract_f(g, k, order[q], o);
     if (plan_ok(g, Q, &why)) return Q;
   }
   return P;   // the caller reports why it is invalid
@@ -505,6 +543,7 @@ QArgs plan_q(const Geo& g, int k, long long* qsize) {
 // ---------------------------------------------------------------------------
 struct ifctn_job {
   Geo g;
+  PlanOpts opts;              // tuning options the job was planned with
   hipStream_t stream = nullptr;
   unsigned char* arena = nullptr;
   size_t arena_bytes = 0;
@@ -550,21 +589,10 @@ struct Sizes {
   size_t x, xb, bits, G, W64, Wc, Q, Upart, Ufin, Hpart, hcnt, normpart, dgpart, stats, flag, qitems, total;
 };
 
-// A factor block takes the phased form when one of its Gram weight sets is
-// large: the one-workgroup-per-column kernel would stream all of Q_{k,i}
-// through each of only I_k workgroups.
-constexpr long long kPhasedMinDefault = 16384;
-std::atomic<long long> g_phased_min{-1};
-
-long long phased_min() {
-  long long v = g_phased_min.load();
-  return v >= 0 ? v : kPhasedMinDefault;
-}
-
-bool use_phased(const Geo& g, const QArgs& Q, int k) {
+bool use_phased(const Geo& g, const QArgs& Q, int k, const PlanOpts& o) {
   long long m = 0;
   for (int t = 0; t < g.N - 1; ++t) m = std::max(m, Q.it[t].D * (long long)(Q.it[t].R * (Q.it[t].R + 1) / 2));
-  if (m >= phased_min()) return true;
+  if (m >= o.phased_min) return true;
   // the per-column kernel keeps the column's edge rows of every other mode in
   // LDS; when a long mode makes them too large, the phased form (which reads
   // them from HBM) takes the block
@@ -587,7 +615,7 @@ int hp_width(int Ik) {
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
+Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o) {
   Sizes s;
   s.x = al256(g.nX * g.esz);
   s.xb = g.bf16 ? al256(g.nX * 2) : 0;
@@ -598,7 +626,7 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
   long long qmax = 0, upmax = 0, ufmax = 0, hmax = 0, nnorm = 0, ndg = 0;
   const bool dbg = std::getenv("IFCTN_DEBUG_PLAN") != nullptr;
   for (int k = 0; k < g.N; ++k) {
-    ContractPlan P = plan_contract(g, k);
+    ContractPlan P = plan_contract(g, k, o);
     long long qs = 0;
     QArgs Q = plan_q(g, k, &qs);
     if (dbg) {
@@ -616,7 +644,7 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp) {
     qmax = std::max(qmax, qs);
     upmax = std::max(upmax, (long long)P.a.S * P.a.FS * P.a.Ik * P.a.Rprod);
     ufmax = std::max(ufmax, (long long)P.a.Ik * P.a.Rprod);
-    if (use_phased(g, Q, k))
+    if (use_phased(g, Q, k, o))
       for (int t = 0; t < g.N - 1; ++t) {
         const long long ks = (Q.it[t].D + HP_DC - 1) / HP_DC;
         hmax = std::max(hmax, ks * g.dims[k] * (long long)(Q.it[t].R * (Q.it[t].R + 1) / 2));
@@ -712,7 +740,7 @@ void build_solve_plans(ifctn_job* J) {
       B.w_sy = w.s2;
       ++t;
     }
-    J->phased[k] = use_phased(g, Q, k);
+    J->phased[k] = use_phased(g, Q, k, J->opts);
     for (int t2 = 0; t2 < a.nsub; ++t2) {
       PhaseArgs& h = J->pplan[k][t2];
       std::memset(&h, 0, sizeof(h));
@@ -944,11 +972,17 @@ size_t ifctn_num_factor_entries(const ifctn_params* params) {
   return (size_t)g.nG;
 }
 
-size_t ifctn_workspace_bytes(const ifctn_params* params) {
+size_t ifctn_workspace_bytes(const ifctn_params* params) { return job_bytes(params, current_opts()); }
+
+}  // extern "C"
+
+namespace ifctn {
+
+size_t job_bytes(const ifctn_params* params, const PlanOpts& o) {
   Geo g;
   if (make_geo(params, &g) != IFCTN_OK) return 0;
   ContractPlan cp[MAXN];
-  const Sizes s = job_sizes(g, cp, nullptr);
+  const Sizes s = job_sizes(g, cp, nullptr, o);
   const char* why = "";
   for (int k = 0; k < g.N; ++k)
     if (!plan_ok(g, cp[k], &why)) {
@@ -957,6 +991,10 @@ size_t ifctn_workspace_bytes(const ifctn_params* params) {
     }
   return s.total;
 }
+
+}  // namespace ifctn
+
+extern "C" {
 
 ifctn_status ifctn_destroy(ifctn_job* job) {
   if (!job) return IFCTN_OK;
@@ -973,7 +1011,7 @@ namespace ifctn {
 
 ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
                       const double* G0_host, hipStream_t stream, unsigned char* pool, size_t pool_bytes,
-                      bool check_now, ifctn_job** out) {
+                      bool check_now, const PlanOpts& opts, ifctn_job** out) {
   if (!out) return fail(IFCTN_E_INVAL, "out is NULL");
   *out = nullptr;
   Geo g;
@@ -984,7 +1022,8 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   ifctn_job* J = new ifctn_job();
   J->g = g;
   J->stream = (hipStream_t)stream;
-  const Sizes s = job_sizes(g, J->cplan, J->qplan);
+  J->opts = opts;
+  const Sizes s = job_sizes(g, J->cplan, J->qplan, opts);
   for (int k = 0; k < g.N; ++k) {
     const char* why = "";
     if (!plan_ok(g, J->cplan[k], &why)) {
@@ -1044,9 +1083,9 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   }
   J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
   build_solve_plans(J);
-  J->onelaunch = phased_onelaunch();
+  J->onelaunch = opts.onelaunch;
   for (int k = 0; k < g.N; ++k) {
-    J->merge[k] = merge_gram();
+    J->merge[k] = opts.merge_gram;
     J->splan[k].stop = J->flag + 1;
     for (int t = 0; t < g.N - 1; ++t) J->pplan[k][t].stop = J->flag + 1;
   }
@@ -1097,8 +1136,6 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   *out = J;
   return IFCTN_OK;
 }
-
-size_t job_bytes(const ifctn_params* params) { return ifctn_workspace_bytes(params); }
 
 hipError_t job_sweeps(ifctn_job* J, int n) {
   for (int q = 0; q < n; ++q) {
@@ -1151,7 +1188,7 @@ extern "C" {
 
 ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
                         const double* G0_host, void* stream, ifctn_job** out) {
-  return job_open(params, O_dev, mask_dev, G0_host, (hipStream_t)stream, nullptr, 0, true, out);
+  return job_open(params, O_dev, mask_dev, G0_host, (hipStream_t)stream, nullptr, 0, true, current_opts(), out);
 }
 
 
@@ -1286,6 +1323,10 @@ ifctn_status ifctn_set_option(const char* name, int64_t value) {
   }
   if (std::strcmp(name, "contract_emin") == 0) {
     g_contract_emin.store(value);
+    return IFCTN_OK;
+  }
+  if (std::strcmp(name, "inject_admit_failures") == 0) {
+    g_inject_admit.store(value > 0 ? value : 0);
     return IFCTN_OK;
   }
   if (std::strcmp(name, "contract_jmax") == 0) {

@@ -10,15 +10,27 @@
 
 namespace ifctn {
 
-// Device bytes of one job (ifctn_workspace_bytes); 0 for invalid params.
-size_t job_bytes(const ifctn_params* params);
+// Tuning options of ifctn_set_option that shape a job's work plans and so
+// its size.  A job is sized and created with one snapshot of them.
+struct PlanOpts {
+  long long phased_min, contract_div, contract_emin, contract_jmax;
+  bool merge_gram, onelaunch;
+};
+PlanOpts current_opts();
+
+// Fault injection for the serving tests (option "inject_admit_failures"):
+// true while injected admission failures remain, consuming one.
+bool take_injected_admit_failure();
+
+// Device bytes of one job planned with these options; 0 for invalid params.
+size_t job_bytes(const ifctn_params* params, const PlanOpts& opts);
 
 // Create a job.  pool != nullptr: the job lives in [pool, pool + pool_bytes)
 // (no allocation; the caller owns that memory).  check_now: synchronise and
 // reject non-finite observed data at once; otherwise flag word 0 reports it.
 ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
                       const double* G0_host, hipStream_t stream, unsigned char* pool, size_t pool_bytes,
-                      bool check_now, ifctn_job** out);
+                      bool check_now, const PlanOpts& opts, ifctn_job** out);
 
 hipError_t job_sweeps(ifctn_job* J, int n);       // n sweeps, X step of the last one left pending
 hipError_t job_x_step(ifctn_job* J);              // the pending X step (and stop test), if any

@@ -78,6 +78,7 @@ class PoolAlloc {
 struct Pending {
   ifctn_request req;
   std::vector<double> G0;
+  PlanOpts opts;   // the tuning options at submit: admission plans the job as it was sized
   size_t bytes;
   double t_submit;
 };
@@ -224,8 +225,10 @@ bool ifctn_server::admit() {
     res.push_back(r);
     any = true;
     const ifctn_request& q = r->p.req;
-    ifctn_status st = job_open(&q.params, q.O_dev, q.mask_dev, r->p.G0.data(), streams[r->stream], pool + off,
-                               r->p.bytes, false, &r->J);
+    ifctn_status st = take_injected_admit_failure()
+                          ? set_error(IFCTN_E_NOMEM, "injected admission failure")
+                          : job_open(&q.params, q.O_dev, q.mask_dev, r->p.G0.data(), streams[r->stream],
+                                     pool + off, r->p.bytes, false, r->p.opts, &r->J);
     if (st != IFCTN_OK) {
       r->J = nullptr;
       finish(*r, st, true);
@@ -277,6 +280,7 @@ hipError_t ifctn_server::issue(Resident& r) {
 }
 
 void ifctn_server::step(Resident& r, bool* progressed) {
+  if (r.finished) return;   // failed at admission, or done: removed after this pass
   if (r.waiting) {
     const hipError_t q = hipEventQuery(r.ev);
     if (q == hipErrorNotReady) return;
@@ -388,13 +392,15 @@ ifctn_status ifctn_server_submit(ifctn_server* S, const ifctn_request* req) {
     return set_error(IFCTN_E_INVAL, "O_dev, mask_dev, G0_host and X_out_dev are required");
   if (req->t_max < 0) return set_error(IFCTN_E_INVAL, "t_max < 0");
   if (!(req->eps >= 0.0)) return set_error(IFCTN_E_INVAL, "eps < 0");
-  const size_t bytes = job_bytes(&req->params);
+  const PlanOpts opts = current_opts();
+  const size_t bytes = job_bytes(&req->params, opts);
   if (bytes == 0) return IFCTN_E_INVAL;  // message set by the params check
   if (PoolAlloc::rounded(bytes) > S->cfg.hbm_budget_bytes)
     return set_error(IFCTN_E_NOMEM, "the job needs more device memory than the server's whole budget");
   Pending p;
   p.req = *req;
   p.G0.assign(req->G0_host, req->G0_host + ifctn_num_factor_entries(&req->params));
+  p.opts = opts;
   p.bytes = bytes;
   p.t_submit = S->now();
   {

@@ -145,3 +145,43 @@ def test_bf16_refine_msi256_full_size():
     assert e32 < 1e-5
     assert e < 1e-3
     assert rse <= 1.01 * rse32
+
+
+@pytest.mark.parametrize("dims,R", [((14, 12, 9, 11), 3), ((9, 8, 7, 6, 8), 2), ((6, 7, 5, 6, 5), 4)])
+def test_bf16_refine_orders_4_5_match_oracle(dims, R):
+    """Several bfloat16 sweeps and then float32 refinement sweeps at orders 4
+    and 5 (the served mix runs this precision on such tensors): 15 + 15
+    sweeps against 30 oracle sweeps.  These small random tensors are still
+    moving fast at sweep 30, so half of the sweeps refine in float32 (with a
+    third, the order-4 case measured 1.2e-3)."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem(dims, W.uniform_ranks(len(dims), R), seed=61 + R, keep=0.4)
+    print(f"[case] bf16 refine dims={dims} R={R}", flush=True)
+    O64 = p.O.astype(np.float64)
+    Xo, _, _ = oracle.pam(O64, p.mask, p.G0, p.dims, rho=p.rho, t_max=30, eps=0.0)
+    X, st = ifctn.complete(p.O, p.mask, p.G0, p.dims, p.ranks, t_max=30, precision=ifctn.IFCTN_BF16_REFINE,
+                           refine_sweeps=15)
+    e = relerr(X.cpu().numpy(), Xo)
+    print(f"{dims} R={R}: bf16(15)+fp32(15) vs oracle(30): {e:.2e}")
+    assert st["sweeps_done"] == 30
+    assert e < 1e-3
+    m = p.mask.astype(bool)
+    assert np.array_equal(X.cpu().numpy()[m], p.O[m])
+
+
+def test_bf16_refine_video144_full_size():
+    """The order-4 video-shaped workload at full size (144 x 176 x 3 x 50):
+    12 bfloat16 + 8 float32 sweeps against 20 oracle sweeps, and the FP32
+    path after the same 20 sweeps."""
+    from paper_2511_16358_amd import ifctn
+    p = W.problem("video144", 0, lambda d, r, G: oracle.reconstruct(G, d))
+    O64 = p.O.astype(np.float64)
+    Xo, _, _ = oracle.pam(O64, p.mask, p.G0, p.dims, rho=p.rho, t_max=20, eps=0.0)
+    X, st = ifctn.complete(p.O, p.mask, p.G0, p.dims, p.ranks, t_max=20, precision=ifctn.IFCTN_BF16_REFINE,
+                           refine_sweeps=8)
+    X32, _ = ifctn.complete(p.O, p.mask, p.G0, p.dims, p.ranks, t_max=20)
+    e = relerr(X.cpu().numpy(), Xo)
+    e32 = relerr(X32.cpu().numpy(), Xo)
+    print(f"video144 bf16(12)+fp32(8) vs oracle(20): {e:.2e} (fp32 path {e32:.2e})")
+    assert e32 < 1e-5
+    assert e < 1e-3

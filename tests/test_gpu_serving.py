@@ -192,3 +192,61 @@ def test_rank_grid_batch_equals_alone():
         X, st = ifctn.complete(p.O, p.mask, G0, p.dims, r, t_max=40, eps=1e-4)
         assert np.array_equal(got[q]["X"].cpu().numpy(), X.cpu().numpy()), q
         assert got[q]["stats"]["sweeps_done"] == st["sweeps_done"]
+
+
+def test_served_fp64_rank_grid_matches_oracle():
+    """A rank grid served as one FP64 batch (shared observed tensor and
+    mask): every job against the oracle's Algorithm 1 with the same ranks and
+    initial factors."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem((12, 10, 9), W.uniform_ranks(3, 2), seed=83, keep=0.5)
+    grid = W.rank_grid_msi()
+    O64 = p.O.astype(np.float64)
+    O = torch.as_tensor(O64).cuda()
+    M = torch.as_tensor(p.mask).cuda()
+    G0s = [W.initial_factors_for(p, r, seed=q) for q, r in enumerate(grid)]
+    srv = ifctn.Server(64 << 20, max_active=len(grid), num_streams=4, sweeps_per_round=4)
+    torch.cuda.synchronize()
+    for q, (r, G0) in enumerate(zip(grid, G0s)):
+        srv.submit(O, M, G0, p.dims, r, 15, eps=0.0, precision=ifctn.IFCTN_FP64, tag=q)
+    got = {}
+    for _ in range(300):
+        for c in srv.poll(16, wait_ms=100):
+            got[c["tag"]] = c
+        if len(got) == len(grid):
+            break
+    srv.close()
+    assert len(got) == len(grid)
+    for q, (r, G0) in enumerate(zip(grid, G0s)):
+        Xo, _, ho = oracle.pam(O64, p.mask, G0, p.dims, rho=0.1, t_max=15, eps=0.0)
+        assert got[q]["status"] == ifctn.IFCTN_OK
+        assert relerr(got[q]["X"].cpu().numpy(), Xo) < 1e-10, (q, np.asarray(r).tolist())
+        assert abs(got[q]["stats"]["objective"] - ho[-1]["objective"]) <= 1e-9 * ho[-1]["objective"]
+
+
+def test_failed_admission_reports_and_server_continues():
+    """A request that fails at admission (fault injection: the next
+    admission reports IFCTN_E_NOMEM) is completed with that status, its slot
+    and pool range are returned, and the requests after it run normally."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem((16, 14, 12), W.uniform_ranks(3, 3), seed=91)
+    need = ifctn.workspace_bytes(p.dims, p.ranks)
+    srv = ifctn.Server(hbm_budget_bytes=need + 4096, max_active=1, num_streams=1, sweeps_per_round=3)
+    ifctn.set_option("inject_admit_failures", 1)
+    try:
+        for q in range(3):
+            srv.submit(p.O, p.mask, p.G0, p.dims, p.ranks, 9, tag=q)
+        got = {}
+        for _ in range(300):
+            for c in srv.poll(8, wait_ms=100):
+                got[c["tag"]] = c
+            if len(got) == 3:
+                break
+    finally:
+        ifctn.set_option("inject_admit_failures", 0)
+        srv.close()
+    assert got[0]["status"] == ifctn.IFCTN_E_NOMEM
+    X, st = ifctn.complete(p.O, p.mask, p.G0, p.dims, p.ranks, t_max=9)
+    for q in (1, 2):
+        assert got[q]["status"] == ifctn.IFCTN_OK
+        assert np.array_equal(got[q]["X"].cpu().numpy(), X.cpu().numpy())
