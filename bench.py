@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--no-tuning", action="store_true", help="skip the rank-grid tuning leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sweeps", type=int, default=0, help="oracle sweeps (0 = auto, ~10-30 s)")
+    ap.add_argument("--route", default="auto", choices=["auto", "percolumn", "gamma"],
+                    help="factor-block route: auto (the library's default), the per-column Gram-weight "
+                         "route only, or the Gamma route wherever it fits")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run 5 plain device copies of MIB MiB (scale for the HBM byte counters)")
     return ap.parse_args()
@@ -345,6 +348,8 @@ def main():
     from paper_2511_16358_amd import ifctn
     from paper_2511_16358_amd import workloads as W
 
+    if args.route != "auto":
+        ifctn.set_option("gamma", 0 if args.route == "percolumn" else 2)
     prec = {"fp32": ifctn.IFCTN_FP32, "fp64": ifctn.IFCTN_FP64, "bf16": ifctn.IFCTN_BF16_REFINE}[args.precision]
     esz = {"fp32": 4, "fp64": 8, "bf16": 2}[args.precision]
 

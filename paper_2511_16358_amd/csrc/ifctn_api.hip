@@ -163,7 +163,8 @@ struct ContractPlan {
 constexpr int kTargetBlocks = 1024;
 
 // tuning options (ifctn_set_option): < 0 = default
-std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1}, g_onelaunch{-1}, g_contract_jmax{-1};
+std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1}, g_onelaunch{-1}, g_contract_jmax{-1},
+    g_ugroup{-1}, g_gamma{-1};
 // A factor block takes the phased form when one of its Gram weight sets is
 // large: the one-workgroup-per-column kernel would stream all of Q_{k,i}
 // through each of only I_k workgroups.
@@ -192,6 +193,18 @@ PlanOpts current_opts() {
   // 256 x 256 x 31 workload and on order-4/5 served tensors
   v = g_contract_jmax.load();
   o.contract_jmax = v > 0 ? v : 8;
+  // grouped reduction of the contraction's partial slots: off by default --
+  // every workgroup's device-scope release (an L2 write-back on this chip,
+  // whose L2 is per XCD) made the grouped launches about three times slower;
+  // the Gamma route reduces the partials in parallel in its own launch instead
+  v = g_ugroup.load();
+  o.ugroup = v >= 0 ? v : 0;
+  // Gamma route for the blocks whose Gram weight sets are large (where the
+  // per-column route would take the phased form); with small sets the
+  // per-column route merges its Gram weights into the contraction launch and
+  // needs no launch of its own
+  v = g_gamma.load();
+  o.gamma = v < 0 ? 1 : (int)std::min<long long>(v, 2);
   return o;
 }
 std::atomic<long long> g_inject_admit{0};
@@ -207,6 +220,10 @@ bool take_injected_admit_failure() {
 namespace {
 
 constexpr size_t kMaxLds = 64 << 10;
+// the Gamma-route kernels run few workgroups: they may take most of a
+// compute unit's 160 KB of LDS (their launchers raise the kernel's limit)
+constexpr size_t kMaxLdsGamma = 144 << 10;
+constexpr int GM_VPT_HOST = 8;   // accumulation tiles per wave of the Gamma kernel
 
 // fibre mode f: the contiguous last mode when it is long enough, otherwise
 // the longest mode != k (the Kronecker accumulation costs Rprod / I_f per element)
@@ -536,6 +553,222 @@ QArgs plan_q(const Geo& g, int k, long long* qsize) {
   return a;
 }
 
+// Gamma route of factor block k (see GammaPlan): the modes other than k in
+// Gamma order, the prefix split over workgroups and the LDS layout of one
+// workgroup.  Returns false when Gamma_k or a workgroup's tables are too large.
+bool plan_gamma(const Geo& g, int k, GammaPlan* gp) {
+  std::memset(gp, 0, sizeof(*gp));
+  const int N = g.N, n = N - 1;
+  int srt[MAXN - 1], c = 0;
+  for (int q = 0; q < N; ++q)
+    if (q != k) srt[c++] = q;
+  std::stable_sort(srt, srt + n, [&](int x, int y) { return g.dims[x] < g.dims[y]; });
+  int om[MAXN - 1];
+  if (n == 1) {
+    om[0] = srt[0];
+  } else if (n == 2) {            // prefix: the shorter mode; y: the longer
+    om[0] = srt[0];
+    om[1] = srt[1];
+  } else if (n == 3) {            // prefix: middle; x: shortest; y: longest
+    om[0] = srt[1];
+    om[1] = srt[0];
+    om[2] = srt[2];
+  } else {                        // prefix: the two middle modes
+    om[0] = srt[1];
+    om[1] = srt[2];
+    om[2] = srt[0];
+    om[3] = srt[3];
+  }
+  gp->n = n;
+  gp->npre = n >= 3 ? n - 2 : 1;
+  gp->hasx = n >= 3 ? 1 : 0;
+  long long P = 1;
+  for (int u = 0; u < n; ++u) {
+    const int m = om[u];
+    gp->mode[u] = m;
+    gp->dim[u] = g.dims[m];
+    gp->rank[u] = g.R[m][k];
+    gp->np[u] = gp->rank[u] * (gp->rank[u] + 1) / 2;
+    gp->goff[u] = g.goff[m][k];
+    P *= gp->np[u];
+  }
+  if (P > GM_PMAX) return false;
+  gp->P = (int)P;
+  int sacc = 1;
+  for (int u = n - 1; u >= 0; --u) {
+    gp->st[u] = sacc;
+    sacc *= gp->np[u];
+  }
+  for (int a = 0; a < n; ++a)
+    for (int b = 0; b < n; ++b)
+      if (a != b) gp->e[a][b] = edge_ref(g, om[a], om[b]);
+  gp->nq = 1;
+  gp->npp = 1;
+  for (int u = 0; u < gp->npre; ++u) {
+    gp->nq *= gp->dim[u];
+    gp->npp *= gp->np[u];
+  }
+  const int py = n - 1, px = n - 2;
+  // LDS of a workgroup with qpw prefix tuples (nqc per chunk) and pyw y pairs
+  auto lds = [&](int qpw, int nqc, int pyw, GammaPlan* o) {
+    int at = 0;
+    o->o_gy = at; at += n >= 2 ? gp->rank[py] * gp->dim[py] : 0;
+    o->o_gx = at; at += gp->hasx ? gp->rank[px] * gp->dim[px] : 0;
+    o->o_wa = at; at += gp->hasx ? gp->dim[px] * gp->dim[py] : (n == 2 ? qpw * gp->dim[py] : 0);
+    o->o_cq = at; at += n >= 3 ? qpw * gp->dim[py] : 0;
+    o->o_wb = at; at += gp->hasx ? qpw * gp->dim[px] : 0;
+    o->o_t = at;  at += gp->hasx ? gp->dim[px] * nqc * pyw : (n == 2 ? nqc * pyw : 0);
+    o->o_y = at;  at += gp->hasx ? nqc * gp->np[px] * pyw : 0;
+    o->o_cp = at; at += qpw * gp->npp;
+    o->o_pr = at; at += (n * MAXP + 1) / 2;
+    return (size_t)at * 8;
+  };
+  // work per prefix tuple (multiply-adds): stage A, stage B, accumulation;
+  // about 2^18 per workgroup: the y pairs split first (no partial sums), then
+  // the prefix tuples (at most GM_QG partial sums per entry)
+  const int npy = n >= 2 ? gp->np[py] : 1;
+  const double costA = n >= 2 ? (gp->hasx ? (double)gp->dim[px] : 1.0) * gp->dim[py] * gp->np[py] : 0.0;
+  const double costB = gp->hasx ? (double)gp->dim[px] * gp->np[px] * gp->np[py] : 0.0;
+  const double total = (double)gp->nq * (costA + costB + (double)P);
+  long long nwt = (long long)std::ceil(total / 32768.0);
+  nwt = std::max<long long>(1, std::min<long long>(nwt, GM_MAXW));
+  int nyg = (int)std::min<long long>(npy, nwt);
+  int pyw = (int)cdiv(npy, nyg);
+  // the accumulation tiles of a workgroup (npp x np_x pyw entries) over its
+  // four waves: at most GM_VPT per wave
+  const int nppx = gp->npp * (gp->hasx ? gp->np[px] : 1);
+  auto tiles = [&](int w) { return (int)(cdiv(gp->npp, 16) * cdiv((long long)nppx / gp->npp * w, 16)); };
+  while (pyw > 1 && tiles(pyw) > 4 * GM_VPT_HOST) pyw = (int)cdiv(pyw, 2);
+  if (tiles(pyw) > 4 * GM_VPT_HOST) return false;
+  nyg = (int)cdiv(npy, pyw);
+  long long nqg = std::max<long long>(1, std::min<long long>({cdiv(nwt, nyg), (long long)GM_QG, gp->nq}));
+  long long qpw = cdiv(gp->nq, nqg);
+  int nqc = 16;
+  for (;;) {
+    nqc = (int)std::min<long long>(16, qpw);
+    while (nqc > 1 && lds((int)qpw, nqc, pyw, gp) > kMaxLdsGamma) --nqc;
+    if (lds((int)qpw, nqc, pyw, gp) <= kMaxLdsGamma) break;
+    if (nqg >= std::min<long long>(GM_QG, gp->nq)) return false;
+    nqg = std::min<long long>({nqg * 2, (long long)GM_QG, gp->nq});
+    qpw = cdiv(gp->nq, nqg);
+  }
+  gp->nqc = nqc;
+  gp->smem = (int)lds((int)qpw, nqc, pyw, gp);
+  gp->qpw = (int)qpw;
+  gp->nqg = (int)cdiv(gp->nq, qpw);
+  gp->nyg = nyg;
+  gp->pyw = pyw;
+  gp->nw = gp->nyg * gp->nqg;
+  return true;
+}
+
+// The Gamma-route solve of block k (see GSolve); false when its LDS does not fit.
+bool plan_gsolve(const Geo& g, int k, const GammaPlan& gp, GSolve* gs, std::vector<int>* tabv = nullptr) {
+  std::memset(gs, 0, sizeof(*gs));
+  const int N = g.N, n = N - 1;
+  gs->k = k;
+  gs->Ik = g.dims[k];
+  gs->n = n;
+  gs->P = gp.P;
+  gs->rho = g.rho;
+  int um[MAXN - 1], c = 0;
+  for (int q = 0; q < N; ++q)
+    if (q != k) um[c++] = q;
+  int Rprod = 1;
+  for (int t = n - 1; t >= 0; --t) {
+    gs->ust[t] = Rprod;
+    Rprod *= g.R[k][um[t]];
+  }
+  gs->Rprod = Rprod;
+  for (int t = 0; t < n; ++t) {
+    const int m = um[t];
+    gs->R[t] = g.R[k][m];
+    gs->np[t] = gs->R[t] * (gs->R[t] + 1) / 2;
+    gs->dim[t] = g.dims[m];
+    for (int u = 0; u < n; ++u)
+      if (gp.mode[u] == m) gs->gst[t] = gp.st[u];
+    gs->goff_ki[t] = g.goff[k][m];
+    gs->goff_ik[t] = g.goff[m][k];
+    const EdgeRef w = edge_ref(g, k, m);
+    gs->w_off[t] = w.off;
+    gs->w_sj[t] = w.s1;
+    gs->w_sy[t] = w.s2;
+  }
+  int scr = 1, tab = 0;
+  for (int t = 0; t < n; ++t) {
+    int o[MAXN - 1], ob[MAXN - 1], no = 0;
+    for (int u = 0; u < n; ++u)
+      if (u != t) o[no++] = u;
+    for (int q = 0; q < no; ++q) ob[q] = o[q];
+    // largest extent first: the first (largest) intermediate is smallest
+    std::stable_sort(o, o + no, [&](int x, int y) { return gs->np[x] > gs->np[y]; });
+    std::stable_sort(ob, ob + no, [&](int x, int y) { return gs->R[x] > gs->R[y]; });
+    long long hn = gp.P, bn = Rprod;
+    for (int q = 0; q < no; ++q) {
+      (void)0;
+      gs->ord[t][q] = o[q];
+      gs->bord[t][q] = ob[q];
+      hn /= gs->np[o[q]];
+      bn /= gs->R[ob[q]];
+      gs->hnout[t][q] = (int)hn;
+      gs->bnout[t][q] = (int)bn;
+      gs->hoff[t][q] = tab;
+      tab += (int)hn;
+      gs->boff[t][q] = tab;
+      tab += (int)bn;
+      if (q == 0) scr = std::max<long long>({(long long)scr, hn, bn});
+    }
+  }
+  gs->tabtot = tab;
+  gs->scr = (scr + 1) & ~1;
+  // the offset tables: replay each chain's dims and strides
+  std::vector<int> scratch_tab;
+  if (!tabv) tabv = &scratch_tab;
+  {
+    tabv->assign(tab, 0);
+    for (int t = 0; t < n; ++t)
+      for (int which = 0; which < 2; ++which) {
+        int d[MAXN - 1], st[MAXN - 1], alive[MAXN - 1];
+        for (int u = 0; u < n; ++u) {
+          d[u] = which ? gs->R[u] : gs->np[u];
+          st[u] = which ? gs->ust[u] : gs->gst[u];
+          alive[u] = 1;
+        }
+        for (int c = 0; c < n - 1; ++c) {
+          const int uc = which ? gs->bord[t][c] : gs->ord[t][c];
+          (which ? gs->bsc : gs->hsc)[t][c] = st[uc];
+          alive[uc] = 0;
+          const int nout = (which ? gs->bnout : gs->hnout)[t][c];
+          int* out = tabv->data() + (which ? gs->boff : gs->hoff)[t][c];
+          for (int o = 0; o < nout; ++o) {
+            int rem = o, off = 0;
+            for (int u = n - 1; u >= 0; --u)
+              if (alive[u]) {
+                off += (rem % d[u]) * st[u];
+                rem /= d[u];
+              }
+            out[o] = off;
+          }
+          int sacc = 1;
+          for (int u = n - 1; u >= 0; --u)
+            if (alive[u]) {
+              st[u] = sacc;
+              sacc *= d[u];
+            }
+        }
+      }
+  }
+  int gik = 0;
+  for (int t = 0; t < n; ++t) {
+    gs->gik_off[t] = gik;
+    gik += gs->R[t] * gs->dim[t];
+  }
+  gs->gik_tot = gik;
+  gs->gik_lds = (size_t)gsolve_smem(n, gp.P, Rprod, gs->scr, gik, tab) <= kMaxLdsGamma ? 1 : 0;
+  gs->smem = gsolve_smem(n, gp.P, Rprod, gs->scr, gs->gik_lds ? gik : 0, tab);
+  return (size_t)gs->smem <= kMaxLdsGamma;
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -557,6 +790,8 @@ struct ifctn_job {
   void* Wc = nullptr;
   double* Q = nullptr;
   double* Upart = nullptr;
+  double* Ugrp = nullptr;     // group sums of the partial slots (grouped reduction)
+  int* ucnt = nullptr;
   double* Ufin = nullptr;
   double* Hpart = nullptr;
   int* hcnt = nullptr;
@@ -569,6 +804,15 @@ struct ifctn_job {
   QArgs qplan[MAXN];
   SolveArgs splan[MAXN];
   bool phased[MAXN] = {};
+  bool groute[MAXN] = {};      // factor block by the Gamma route
+  GammaPlan gplan[MAXN];       // host copies (device copies at dgp / dgs)
+  GSolve gsol[MAXN];
+  GammaPlan* dgp = nullptr;
+  GSolve* dgs = nullptr;
+  std::vector<int> htab;       // host copy of the Gamma-route offset tables (source of an async copy)
+  double* gamma = nullptr;
+  double* gmpart = nullptr;
+  int* gmcnt = nullptr;
   bool merge[MAXN] = {};       // Gram weights inside the contraction launch
   PhaseArgs pplan[MAXN][MAXN - 1];
   int nnorm = 0, ndg = 0;
@@ -586,7 +830,8 @@ struct ifctn_job {
 namespace {
 
 struct Sizes {
-  size_t x, xb, bits, G, W64, Wc, Q, Upart, Ufin, Hpart, hcnt, normpart, dgpart, stats, flag, qitems, total;
+  size_t x, xb, bits, G, W64, Wc, Q, Upart, Ugrp, ucnt, Ufin, Hpart, hcnt, normpart, dgpart, stats, flag, qitems;
+  size_t gamma, gmpart, gmcnt, grec, gtab, total;
 };
 
 bool use_phased(const Geo& g, const QArgs& Q, int k, const PlanOpts& o) {
@@ -615,7 +860,8 @@ int hp_width(int Ik) {
 
 size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
-Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o) {
+Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o, GammaPlan* gpl = nullptr,
+                GSolve* gsl = nullptr, bool* groute = nullptr) {
   Sizes s;
   s.x = al256(g.nX * g.esz);
   s.xb = g.bf16 ? al256(g.nX * 2) : 0;
@@ -623,10 +869,18 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o) {
   s.G = al256(g.nG * 8);
   s.W64 = al256(g.nW * 8);
   s.Wc = al256(g.nW * g.esz);
-  long long qmax = 0, upmax = 0, ufmax = 0, hmax = 0, nnorm = 0, ndg = 0;
+  long long qmax = 0, upmax = 0, ugmax = 0, ucmax = 0, ufmax = 0, hmax = 0, nnorm = 0, ndg = 0;
+  long long gmP = 0, gmpart = 0, gmcnt = 0, gtab = 0;
   const bool dbg = std::getenv("IFCTN_DEBUG_PLAN") != nullptr;
   for (int k = 0; k < g.N; ++k) {
     ContractPlan P = plan_contract(g, k, o);
+    {
+      const long long St = (long long)P.a.S * P.a.FS;
+      if (o.ugroup > 1 && St > o.ugroup) {
+        P.a.ugrp = (int)o.ugroup;
+        P.a.ngrp = (int)cdiv(St, o.ugroup);
+      }
+    }
     long long qs = 0;
     QArgs Q = plan_q(g, k, &qs);
     if (dbg) {
@@ -641,10 +895,26 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o) {
     }
     if (cp) cp[k] = P;
     if (qp) qp[k] = Q;
+    GammaPlan gpk;
+    GSolve gsk;
+    const bool gr = o.gamma > 0 && (o.gamma == 2 || use_phased(g, Q, k, o)) && plan_gamma(g, k, &gpk) &&
+                    plan_gsolve(g, k, gpk, &gsk);
+    if (groute) groute[k] = gr;
+    if (gr) {
+      if (gpl) gpl[k] = gpk;
+      if (gsl) gsl[k] = gsk;
+      gmP = std::max<long long>(gmP, gpk.P);
+      gmpart = std::max<long long>(gmpart, (long long)gpk.nqg * gpk.P);
+      gmcnt = std::max<long long>(gmcnt, gpk.nyg);
+      gtab += gsk.tabtot;
+      qs = 0;                        // no Gram weight sets for this block
+    }
     qmax = std::max(qmax, qs);
     upmax = std::max(upmax, (long long)P.a.S * P.a.FS * P.a.Ik * P.a.Rprod);
+    ugmax = std::max(ugmax, (long long)P.a.ngrp * P.a.Ik * P.a.Rprod);
+    ucmax = std::max(ucmax, (long long)P.a.ngrp * P.a.JT);
     ufmax = std::max(ufmax, (long long)P.a.Ik * P.a.Rprod);
-    if (use_phased(g, Q, k, o))
+    if (!gr && use_phased(g, Q, k, o))
       for (int t = 0; t < g.N - 1; ++t) {
         const long long ks = (Q.it[t].D + HP_DC - 1) / HP_DC;
         hmax = std::max(hmax, ks * g.dims[k] * (long long)(Q.it[t].R * (Q.it[t].R + 1) / 2));
@@ -654,6 +924,8 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o) {
   }
   s.Q = al256(qmax * 8);
   s.Upart = al256(upmax * 8);
+  s.Ugrp = al256(ugmax * 8);
+  s.ucnt = al256(ucmax * 4);
   s.Ufin = al256(ufmax * 8);
   s.Hpart = al256(hmax * 8);
   long long ikmax = 1;
@@ -664,9 +936,14 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o) {
   s.stats = al256(8 * 8);
   s.flag = al256(16);
   s.qitems = al256(sizeof(QItem) * MAXN * (MAXN - 1));
-  s.total = s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ufin + s.Hpart + s.hcnt + s.normpart + s.dgpart +
-            s.stats + s.flag +
-            s.qitems;
+  s.gamma = al256(gmP * 8);
+  s.gmpart = al256(gmpart * 8);
+  s.gmcnt = al256(gmcnt * 4);
+  s.grec = al256(sizeof(GammaPlan) * MAXN) + al256(sizeof(GSolve) * MAXN);
+  s.gtab = al256(gtab * 4);
+  s.total = s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ugrp + s.ucnt + s.Ufin + s.Hpart + s.hcnt +
+            s.normpart + s.dgpart +
+            s.stats + s.flag + s.qitems + s.gamma + s.gmpart + s.gmcnt + s.grec + s.gtab;
   return s;
 }
 
@@ -704,8 +981,8 @@ void build_solve_plans(ifctn_job* J) {
     }
     a.rowtot = ro;
     a.Rprod = P.a.Rprod;
-    a.S = P.a.S * P.a.FS;
-    a.Upart = J->Upart;
+    a.S = P.a.ugrp ? P.a.ngrp : P.a.S * P.a.FS;
+    a.Upart = P.a.ugrp ? J->Ugrp : J->Upart;
     a.W64 = J->W64;
     a.Wc = J->Wc;
     a.G = J->G;
@@ -805,8 +1082,9 @@ struct ContractCall {
 // contraction launch (same inputs, no ordering between them), for the
 // layout-specialised contraction kernels.
 bool gram_merged(const ifctn_job* J, int k) {
-  return J->cplan[k].a.kind != 0 && J->qplan[k].blk0[J->qplan[k].ni] > 0 && J->merge[k];
+  return !J->groute[k] && J->cplan[k].a.kind != 0 && J->qplan[k].blk0[J->qplan[k].ni] > 0 && J->merge[k];
 }
+
 
 hipError_t do_contract(ifctn_job* J, const void* c) {
   const ContractCall* cc = (const ContractCall*)c;
@@ -831,9 +1109,15 @@ hipError_t do_contract(ifctn_job* J, const void* c) {
 
 hipError_t do_gram(ifctn_job* J, const void* c) { return launch_q(*(const QArgs*)c, J->stream); }
 
+hipError_t do_gamma(ifctn_job* J, const void* c) {
+  const int k = *(const int*)c;
+  return launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream);
+}
+
 hipError_t do_solve(ifctn_job* J, const void* c) {
   const SolveArgs* a = (const SolveArgs*)c;
   const int k = a->k;
+  if (J->groute[k]) return launch_solve_gamma(J->g.dtype, J->gsol[k], J->dgs + k, J->stream);
   if (!J->phased[k]) return launch_solve(J->g.dtype, *a, J->stream);
   hipError_t e = launch_urow(*a, J->Ufin, J->stream);
   for (int t = 0; t < a->nsub && e == hipSuccess; ++t) {
@@ -854,7 +1138,7 @@ hipError_t run_sweep(ifctn_job* J) {
   const int N = J->g.N;
   hipError_t e;
   for (int k = 0; k < N; ++k) {
-    if (!gram_merged(J, k)) {
+    if (!J->groute[k] && !gram_merged(J, k)) {
       e = timed(J, KC_GRAM, do_gram, &J->qplan[k]);
       if (e != hipSuccess) return e;
     }
@@ -863,6 +1147,10 @@ hipError_t run_sweep(ifctn_job* J) {
     if (e != hipSuccess) return e;
     if (cc.upd && J->dev_stop) {
       e = launch_stop_test(J->normpart, J->nnorm, J->stop_eps, J->flag + 1, J->stream);
+      if (e != hipSuccess) return e;
+    }
+    if (J->groute[k]) {              // Gamma_k and the U rows, then the solve
+      e = timed(J, KC_GRAM, do_gamma, &k);
       if (e != hipSuccess) return e;
     }
     e = timed(J, KC_SOLVE, do_solve, &J->splan[k]);
@@ -1023,7 +1311,7 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   J->g = g;
   J->stream = (hipStream_t)stream;
   J->opts = opts;
-  const Sizes s = job_sizes(g, J->cplan, J->qplan, opts);
+  const Sizes s = job_sizes(g, J->cplan, J->qplan, opts, J->gplan, J->gsol, J->groute);
   for (int k = 0; k < g.N; ++k) {
     const char* why = "";
     if (!plan_ok(g, J->cplan[k], &why)) {
@@ -1057,6 +1345,8 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   J->Wc = p;                     p += s.Wc;
   J->Q = (double*)p;             p += s.Q;
   J->Upart = (double*)p;         p += s.Upart;
+  J->Ugrp = (double*)p;          p += s.Ugrp;
+  J->ucnt = (int*)p;             p += s.ucnt;
   J->Ufin = (double*)p;          p += s.Ufin;
   J->Hpart = (double*)p;         p += s.Hpart;
   J->hcnt = (int*)p;             p += s.hcnt;
@@ -1065,6 +1355,13 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   J->stats5 = (double*)p;        p += s.stats;
   J->flag = (int*)p;             p += s.flag;
   QItem* dq = (QItem*)p;         p += s.qitems;
+  J->gamma = (double*)p;         p += s.gamma;
+  J->gmpart = (double*)p;        p += s.gmpart;
+  J->gmcnt = (int*)p;            p += s.gmcnt;
+  J->dgp = (GammaPlan*)p;        p += al256(sizeof(GammaPlan) * MAXN);
+  J->dgs = (GSolve*)p;           p += al256(sizeof(GSolve) * MAXN);
+  int* dtab = (int*)p;           p += s.gtab;
+  std::vector<int>& htab = J->htab;
   J->bf16_phase = g.bf16;
   for (int k = 0; k < g.N; ++k) {
     ContractArgs& a = J->cplan[k].a;
@@ -1073,6 +1370,8 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
     a.Wc = J->Wc;
     a.G = J->G;
     a.Upart = J->Upart;
+    a.Ugrp = J->Ugrp;
+    a.ucnt = J->ucnt;
     a.normpart = J->normpart;
     J->qplan[k].W64 = J->W64;
     J->qplan[k].G = J->G;
@@ -1083,6 +1382,44 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   }
   J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
   build_solve_plans(J);
+  for (int k = 0; k < g.N; ++k) {
+    if (!J->groute[k]) continue;
+    GammaPlan& gp = J->gplan[k];
+    gp.W64 = J->W64;
+    gp.G = J->G;
+    gp.part = J->gmpart;
+    gp.gamma = J->gamma;
+    gp.cnt = J->gmcnt;
+    const ContractArgs& ca = J->cplan[k].a;
+    gp.S = ca.ugrp ? ca.ngrp : ca.S * ca.FS;
+    gp.Upart = ca.ugrp ? J->Ugrp : J->Upart;
+    gp.nout = (long long)ca.Ik * ca.Rprod;
+    // slices of about 8 slots (one batch of loads each), 4..64 per output
+    gp.us = 4;
+    while (gp.us < 64 && (long long)gp.us * 8 < gp.S) gp.us *= 2;
+    gp.nuw = (int)cdiv(gp.nout, NT / gp.us);
+    gp.Ufin = J->Ufin;
+    GSolve& gs = J->gsol[k];
+    gs.S = 1;                        // the U rows arrive reduced (Ufin)
+    gs.Upart = J->Ufin;
+    gs.gamma = J->gamma;
+    gs.W64 = J->W64;
+    gs.Wc = J->Wc;
+    gs.G = J->G;
+    gs.dgpart = J->splan[k].dgpart;
+    gs.stop = J->flag + 1;
+    J->phased[k] = false;
+    std::vector<int> tk;
+    GSolve again;
+    plan_gsolve(g, k, gp, &again, &tk);          // the same plan, with its offset tables
+    for (int t = 0; t < g.N - 1; ++t)
+      for (int c = 0; c < g.N - 2; ++c) {
+        gs.hsc[t][c] = again.hsc[t][c];
+        gs.bsc[t][c] = again.bsc[t][c];
+      }
+    gs.tab = dtab + htab.size();
+    htab.insert(htab.end(), tk.begin(), tk.end());
+  }
   J->onelaunch = opts.onelaunch;
   for (int k = 0; k < g.N; ++k) {
     J->merge[k] = opts.merge_gram;
@@ -1090,8 +1427,8 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
     for (int t = 0; t < g.N - 1; ++t) J->pplan[k][t].stop = J->flag + 1;
   }
   for (int k = 0; k < g.N; ++k) {
-    const bool too_big = J->phased[k] ? (size_t)J->splan[k].Rprod * 8 > kMaxLds
-                                      : solve_smem_bytes(J->splan[k]) > kMaxLds;
+    const bool too_big = !J->groute[k] && (J->phased[k] ? (size_t)J->splan[k].Rprod * 8 > kMaxLds
+                                                        : solve_smem_bytes(J->splan[k]) > kMaxLds);
     if (too_big) {
       if (J->own_arena) (void)hipFree(J->arena);
       delete J;
@@ -1112,6 +1449,12 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   INIT_TRY(hipMemsetAsync(J->dgpart, 0, s.dgpart, J->stream));
   INIT_TRY(hipMemsetAsync(J->flag, 0, s.flag, J->stream));
   INIT_TRY(hipMemsetAsync(J->hcnt, 0, s.hcnt, J->stream));
+  INIT_TRY(hipMemsetAsync(J->ucnt, 0, s.ucnt, J->stream));
+  INIT_TRY(hipMemsetAsync(J->gmcnt, 0, s.gmcnt, J->stream));
+  INIT_TRY(hipMemcpyAsync(J->dgp, J->gplan, sizeof(GammaPlan) * MAXN, hipMemcpyHostToDevice, J->stream));
+  INIT_TRY(hipMemcpyAsync(J->dgs, J->gsol, sizeof(GSolve) * MAXN, hipMemcpyHostToDevice, J->stream));
+  if (!htab.empty())
+    INIT_TRY(hipMemcpyAsync(dtab, htab.data(), htab.size() * sizeof(int), hipMemcpyHostToDevice, J->stream));
   INIT_TRY(hipMemcpyAsync(J->G, G0_host, g.nG * 8, hipMemcpyHostToDevice, J->stream));
   for (int k = 0; k < g.N; ++k)
     INIT_TRY(hipMemcpyAsync((void*)J->qplan[k].dit, J->qplan[k].it, sizeof(QItem) * (MAXN - 1),
@@ -1323,6 +1666,14 @@ ifctn_status ifctn_set_option(const char* name, int64_t value) {
   }
   if (std::strcmp(name, "contract_emin") == 0) {
     g_contract_emin.store(value);
+    return IFCTN_OK;
+  }
+  if (std::strcmp(name, "gamma") == 0) {
+    g_gamma.store(value < 0 ? -1 : value);
+    return IFCTN_OK;
+  }
+  if (std::strcmp(name, "ugroup") == 0) {
+    g_ugroup.store(value < 0 ? -1 : value);
     return IFCTN_OK;
   }
   if (std::strcmp(name, "inject_admit_failures") == 0) {

@@ -217,6 +217,33 @@ __device__ __forceinline__ void for_batched(int n, Load load, Use use) {
       if (eb + u * NT < n) use(eb + u * NT, v[u]);
   }
 }
+// Grouped reduction of the partial slots (ContractArgs::ugrp): called by every
+// contraction workgroup after its partial slot is written.  The workgroup
+// releases its writes and counts itself in; the last of the group's
+// workgroups to arrive -- every slot of the group is then written and
+// visible -- adds the group's slots in slot order.  No workgroup waits for
+// another.  Workgroup-uniform: every thread returns together.
+__device__ __forceinline__ void group_partials(const ContractArgs& a, int jt, int slot, int j0, int jcnt) {
+  __shared__ int last;
+  const int St = a.S * a.FS;
+  const int g = slot / a.ugrp, lo = g * a.ugrp, hi = min(St, lo + a.ugrp);
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(&a.ucnt[jt * a.ngrp + g], 1) == hi - lo - 1 ? 1 : 0;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int Rprod = a.Rprod, n = jcnt * Rprod;
+  const long long stride = (long long)a.Ik * Rprod;
+  for (int e = threadIdx.x; e < n; e += NT) {
+    const int jl = e / Rprod, c = e - jl * Rprod;
+    const double* up = a.Upart + ((long long)lo * a.Ik + j0 + jl) * Rprod + c;
+    a.Ugrp[((long long)g * a.Ik + j0 + jl) * Rprod + c] = ordered_sum<16>(
+        0.0, hi - lo, [&](int q) { return up[(long long)q * stride]; }, [](int, double x) { return x; });
+  }
+  if (threadIdx.x == 0) a.ucnt[jt * a.ngrp + g] = 0;   // ready for the next launch (stream order)
+}
+
 // --------------------------------------------------------------------------
 // K3 (+ K6): mode-k contraction, optionally fused with the X step of the
 // previous sweep.
@@ -552,6 +579,7 @@ __global__ __launch_bounds__(NT) void k_contract(ContractArgs a) {
       a.normpart[(long long)bid * 3 + tid] = sum;
     }
   }
+  if (CON && a.ugrp) group_partials(a, jt, sp, j0, jcnt);
 }
 
 // --------------------------------------------------------------------------
@@ -1015,6 +1043,7 @@ __global__ __launch_bounds__(NT) void k_contract_rows(ContractArgs a) {
   }
   if (CON) sl.template write<NC>(a, (double*)(smem + Ly.T), spf, j0);
   if (UPD) block_norms(dx2, x2, f2, red, a.normpart + (long long)bid * 3);
+  if (CON && a.ugrp) group_partials(a, jt, spf, j0, jcnt);
 }
 
 // columns variant (mode k contiguous) ----------------------------------------
@@ -1117,6 +1146,7 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
     __syncthreads();
   }
   sl.template write<NC>(a, (double*)(smem + Ly.T), spf, j0);
+  if (a.ugrp) group_partials(a, jt, spf, j0, jcnt);
 }
 
 // Per-launch timing (events set by set_kernel_events; see ifctn_kernels.hip)

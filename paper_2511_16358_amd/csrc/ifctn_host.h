@@ -14,7 +14,9 @@ namespace ifctn {
 // its size.  A job is sized and created with one snapshot of them.
 struct PlanOpts {
   long long phased_min, contract_div, contract_emin, contract_jmax;
+  long long ugroup;   // partial slots per group of the contraction's grouped reduction (0 = off)
   bool merge_gram, onelaunch;
+  int gamma;          // Gamma route: 0 never, 1 where the block would otherwise be phased, 2 wherever it fits
 };
 PlanOpts current_opts();
 

@@ -73,6 +73,104 @@ struct QArgs {
   const int* stop;            // device stop flag: nonzero = the job has met its stop test
 };
 
+// Gram matrix of the mode-k cherry sub-network (Prop. 1), Gamma_k = Z_k^T Z_k:
+//   Gamma_k(r, r') = sum_{i_{-k}} S_k(i_{-k})^2 prod_{m != k} G_{m,k}(r_m, i_m) G_{m,k}(r'_m, i_m).
+// It depends on every mode m != k only through the unordered pair {r_m, r'_m},
+// so it is stored with one packed pair index per mode (np = R (R + 1) / 2
+// values, p(r, r') = r R - r (r - 1) / 2 + (r' - r) for r <= r'), row-major
+// over the modes in "Gamma order": the prefix modes, then x (orders >= 4),
+// then y (orders >= 3).  Gamma_k needs no X and no factor owned by mode k, so
+// one Gamma_k serves every column and every sub-block of factor block k:
+//   H_j = (I (x) c_j)^T Gamma_k (I (x) c_j),  c_j = Kronecker product of the
+// own-side columns G_{k,m}(:, j), m != k, i -- the Gram term of eq. (updateG).
+constexpr int GM_PMAX = 6144;   // entries of Gamma_k (kept in LDS by the solve)
+constexpr int GM_QG = 8;        // prefix ranges (partial sums per Gamma entry), at most
+constexpr int GM_MAXW = 128;    // workgroups that build one Gamma_k
+
+struct GammaPlan {
+  int n;                        // modes other than k (N - 1)
+  int npre;                     // prefix modes: Gamma positions 0 .. npre-1
+  int hasx;                     // position n - 2 is the x mode (n >= 3)
+  int mode[MAXN - 1], dim[MAXN - 1], rank[MAXN - 1], np[MAXN - 1];
+  long long goff[MAXN - 1];     // G_{m,k} (R x I, row-major) in the packed factors
+  int st[MAXN - 1];             // stride of each position's pair index in Gamma
+  EdgeRef e[MAXN - 1][MAXN - 1];// W(i_a, i_b) for positions a != b
+  int P;                        // entries of Gamma
+  int npp;                      // pair tuples of the prefix modes
+  long long nq;                 // index tuples of the prefix modes
+  int qpw, nqc;                 // prefix tuples per workgroup, per LDS chunk
+  // workgroup w = (y group w % nyg, prefix range w / nyg): the y pair
+  // indices [yg * pyw, +pyw) of Gamma over prefix tuples [qg * qpw, +qpw);
+  // the nqg partial sums of a y group are added by its last workgroup
+  int nyg, pyw, nqg;
+  int nw;                       // nyg * nqg
+  int smem;                     // LDS bytes of a workgroup
+  // LDS offsets (doubles)
+  int o_gy, o_gx, o_wa, o_cq, o_wb, o_t, o_y, o_cp, o_pr;
+  const double* W64;
+  const double* G;
+  double* part;                 // [nqg][P] partial sums (each y group writes its entries)
+  double* gamma;                // [P]
+  int* cnt;                     // [nyg] arrival counters, zero between launches
+  // the same launch reduces the contraction's partial slots of block k into
+  // the U rows: nuw workgroups after the nw Gamma workgroups, NT / us outputs
+  // each, every output summed in us slices of the S slots
+  int nuw, S, us;
+  long long nout;               // I_k * Rprod
+  const double* Upart;          // [S][nout]
+  double* Ufin;                 // [nout]
+};
+
+// Factor block k by the Gamma route: one workgroup per column j; per sub-block (i ascending) H_j from Gamma_k and the current
+// own-side columns (a chain of small contractions in LDS), b_j from the U
+// row, LDL^T, then rows j of every W_{k,m} refreshed at the end of the block.
+struct GSolve {
+  int k, Ik, n, P, Rprod, S;
+  double rho;
+  int R[MAXN - 1], np[MAXN - 1], dim[MAXN - 1];
+  int gst[MAXN - 1];             // Gamma stride of U position t's pair index
+  int ust[MAXN - 1];             // canonical U column stride of U position t
+  int ord[MAXN - 1][MAXN - 2];   // sub-block t: U positions contracted, in order
+  long long goff_ki[MAXN - 1], goff_ik[MAXN - 1];
+  long long w_off[MAXN - 1];
+  int w_sj[MAXN - 1], w_sy[MAXN - 1];
+  int scr;                       // doubles of each per-wave contraction scratch buffer
+  // the contraction chains of sub-block t: for H (c = 0 .. n-2, over Gamma
+  // with the pair weights) and for b (over the U row with the own-side
+  // columns): stage c contracts U position hord/bord[t][c]; its output o
+  // reads the input at tab[hoff/boff[t][c] + o] + q * stride, q < extent
+  int bord[MAXN - 1][MAXN - 2];
+  int hoff[MAXN - 1][MAXN - 2], hnout[MAXN - 1][MAXN - 2], hsc[MAXN - 1][MAXN - 2];
+  int boff[MAXN - 1][MAXN - 2], bnout[MAXN - 1][MAXN - 2], bsc[MAXN - 1][MAXN - 2];
+  int tabtot;                    // ints of all offset tables (LDS copy of tab)
+  const int* tab;                // offset tables, built on the host
+  int gik_lds;                   // 1: the far-side factors G_{i,k} are staged in LDS for the row refresh
+  int gik_off[MAXN - 1];         // their offsets in that LDS region (doubles)
+  int gik_tot;
+  int smem;                      // LDS bytes
+  const double* gamma;
+  const double* Upart;
+  double* W64;
+  void* Wc;
+  double* G;
+  double* dgpart;                // [n][Ik]
+  const int* stop;
+};
+
+// LDS of the Gamma-route solve (one column per workgroup): Gamma_k and the
+// pair tables, the U row, own-side columns, pair weights, four contraction
+// buffers (two for H, two for b), H, b; the far-side factors; the offset
+// tables.
+__host__ __device__ inline int gsolve_wave_doubles(int n, int Rprod, int scr) {
+  const int v = Rprod + n * MAXR + n * MAXP + 4 * scr + MAXP + 3 * MAXR;
+  return (v + 1) & ~1;
+}
+
+__host__ __device__ inline int gsolve_smem(int n, int P, int Rprod, int scr, int gik, int tabtot) {
+  const int prd = (n * MAXP + 1) / 2;
+  return 8 * (P + prd + gsolve_wave_doubles(n, Rprod, scr) + gik + (tabtot + 1) / 2);
+}
+
 // Mode-k contraction U_k(j, r_{-k}) = sum_{i_{-k}} X(i) S_k(i_{-k}) prod_{m != k}
 // G_{m,k}(r_m, i_m), organised by "planes": for a fixed index c of the modes
 // other than k and the fibre mode f, the plane is the I_k x I_f slice of X.
@@ -129,6 +227,13 @@ struct ContractArgs {
   // of the launch (they depend on the same inputs as the contraction)
   int gblocks;
   GramRef gr;
+  // grouped partial sums: with ugrp > 0 the last workgroup of each group of
+  // ugrp consecutive partial slots of a j-tile to finish (arrival counter
+  // ucnt[jt * ngrp + g]) adds the group's slots in slot order into Ugrp[g];
+  // the solve then reduces ngrp slots instead of S * FS
+  int ugrp, ngrp;
+  double* Ugrp;          // [ngrp][I_k][Rprod]
+  int* ucnt;             // [JT][ngrp], zero between launches
 };
 
 // Factor block k (all G_{k,i}, i != k, in ascending i), one workgroup per
@@ -234,6 +339,9 @@ hipError_t launch_q(const QArgs& a, hipStream_t s);
 void set_kernel_events(hipEvent_t start, hipEvent_t stop);
 bool kernel_events_used();
 hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s);
+// Gamma route: Gamma_k in a launch of its own (gm: device copy of hp), and the solve
+hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* stop, hipStream_t s);
+hipError_t launch_solve_gamma(int dtype, const GSolve& hs, const GSolve* gs, hipStream_t s);
 size_t solve_smem_bytes(const SolveArgs& a);
 // phased factor block: U rows into Ufin, then per sub-block k_hpart + k_solve_col
 hipError_t launch_urow(const SolveArgs& a, double* Ufin, hipStream_t s);

@@ -14,9 +14,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdint>
 
 #include "ifctn_device.h"
+#include "ifctn_gamma.h"
 #include "ifctn_internal.h"
 
 namespace ifctn {
@@ -164,6 +166,24 @@ __device__ __forceinline__ double ldlt_solve(const double* Hs, const double* bs,
     const double e = x[r] - gold[r];
     dg += e * e;
   }
+  return dg;
+}
+
+// The same solve, for the Gamma route: also writes the pair weights of the
+// new column, mult(p) x_r x_r' for the pairs p = {r <= r'} in packed order
+// (read by the later sub-blocks of the block).
+template <int R>
+__device__ __forceinline__ double ldlt_solve_pairs(const double* Hs, const double* bs, double rho,
+                                                   const double* gold, double* x_out, double* mg_out) {
+  const double dg = ldlt_solve<R>(Hs, bs, rho, gold, x_out);
+  double x[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) x[r] = x_out[r];
+  int p = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int c = r; c < R; ++c) mg_out[p++] = (r == c ? 1.0 : 2.0) * x[r] * x[c];
   return dg;
 }
 
@@ -376,6 +396,196 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       Wc[ad] = (TC)sum;
     }
     __syncthreads();
+  }
+}
+
+// --------------------------------------------------------------------------
+// K5, Gamma route: Gamma_k = Z_k^T Z_k is built once per factor block (the
+// extra workgroups of the contraction launch, or k_gamma); every column j
+// then forms H_j of each sub-block from Gamma_k and its own-side columns:
+//   H_j(p_t) = sum over the pairs p_u of the other modes u of
+//              prod_u mult(p_u) g_u(r_u) g_u(r'_u) Gamma_k(p),
+// mult = 2 for r_u != r'_u (Gamma_k is symmetric in each pair), by a chain of
+// one-mode contractions in LDS.  One wave per column, four per workgroup; the
+// own-side columns of the block stay in LDS through the Gauss-Seidel chain
+// (the new G_{k,i}(:, j) enters the weights of the later sub-blocks), and
+// rows j of every W_{k,m} are refreshed once, after the chain.
+// --------------------------------------------------------------------------
+__global__ __launch_bounds__(NT) void k_gamma(const GammaPlan* __restrict__ gp, const int* __restrict__ stop) {
+  if (stop && *stop) return;
+  const int b = (int)blockIdx.x, nw = gp->nw;
+  if (b < nw)
+    gamma_block<GM_VPT>(gp, b);
+  else
+    urow_block(gp, b - nw);
+}
+
+// One stage of a contraction chain: out[o] = sum_q v[q] in[tab[o] + q sc].
+// Two outputs per thread at a time (the workgroup's threads over the
+// outputs), eight terms per batch of loads (all of a batch in flight before
+// the first product), terms added in ascending q.
+__device__ __forceinline__ void chain_stage(const double* __restrict__ in, double* __restrict__ out,
+                                            const int* __restrict__ tab, int nout, const double* __restrict__ v,
+                                            int dc, int sc, int lane) {
+  for (int o0 = lane; o0 < nout; o0 += 2 * NT) {
+    const int o1 = min(o0 + NT, nout - 1);
+    const int off0 = tab[o0], off1 = tab[o1];
+    double s0 = 0.0, s1 = 0.0;
+    for (int q0 = 0; q0 < dc; q0 += 8) {
+      double a[8], b0[8], b1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int q = min(q0 + u, dc - 1);
+        a[u] = v[q];
+        b0[u] = in[off0 + q * sc];
+        b1[u] = in[off1 + q * sc];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (q0 + u < dc) {
+          s0 += a[u] * b0[u];
+          s1 += a[u] * b1[u];
+        }
+    }
+    out[o0] = s0;
+    if (o0 + NT < nout) out[o0 + NT] = s1;
+  }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(NT) void k_solve_gamma(const GSolve* __restrict__ gs) {
+  if (gs->stop && *gs->stop) return;
+  extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+  double* sm = (double*)smem;
+  const int tid = threadIdx.x;
+  const int n = gs->n, P = gs->P, Rprod = gs->Rprod, Ik = gs->Ik, scr = gs->scr;
+  const int j = xcd_local((int)blockIdx.x, (int)gridDim.x);   // one column per workgroup
+  const int wd = gsolve_wave_doubles(n, Rprod, scr);
+  double* gam = sm;
+  int* pr = (int*)(sm + P);
+  double* wbase = sm + P + (n * MAXP + 1) / 2;
+  double* urow = wbase;
+  double* g = urow + Rprod;              // [n][MAXR] own-side columns G_{k,m}(:, j)
+  double* mg = g + n * MAXR;             // [n][MAXP] pair weights mult * g g
+  double* h1 = mg + n * MAXP;            // H chain buffers
+  double* h2 = h1 + scr;
+  double* b1 = h2 + scr;                 // b chain buffers
+  double* b2 = b1 + scr;
+  double* Hs = b2 + scr;
+  double* bs = Hs + MAXP;
+  double* gold = bs + MAXR;
+  double* gik = wbase + wd;              // far-side factors (when staged)
+  const bool gl = gs->gik_lds != 0;
+  int* tab = (int*)(gik + (gl ? gs->gik_tot : 0));
+  double* G = gs->G;
+  TC* Wc = (TC*)gs->Wc;
+
+  // loads: Gamma_k and the far-side factors as one index space of segments
+  // (a select over at most five segment bounds per element), the offset
+  // tables, the own-side columns and the U row, in wide batches
+  {
+    const int ntot = P + (gl ? gs->gik_tot : 0);
+    long long sbase[MAXN - 1];
+    int sbeg[MAXN - 1];
+#pragma unroll
+    for (int t = 0; t < MAXN - 1; ++t) {
+      sbase[t] = t < n ? gs->goff_ik[t] : 0;
+      sbeg[t] = t < n ? P + gs->gik_off[t] : ntot;
+    }
+    const double* gma = gs->gamma;
+    for_batched<16>(
+        ntot,
+        [&](int e) {
+          long long a = -1;
+#pragma unroll
+          for (int t = 0; t < MAXN - 1; ++t)
+            if (e >= sbeg[t]) a = sbase[t] + (e - sbeg[t]);
+          return a < 0 ? gma[e] : G[a];
+        },
+        [&](int e, double v) { sm[e < P ? e : (int)(gik - sm) + (e - P)] = v; });
+  }
+  for_batched<8>(gs->tabtot, [&](int e) { return gs->tab[e]; }, [&](int e, int v) { tab[e] = v; });
+  for (int e = tid; e < n * MAXR; e += NT) {
+    const int t = e / MAXR, r = e - t * MAXR;
+    g[e] = r < gs->R[t] ? G[gs->goff_ki[t] + (long long)r * Ik + j] : 0.0;
+  }
+  {
+    const long long stride = (long long)Ik * Rprod;
+    const double* up = gs->Upart + (long long)j * Rprod;
+    for (int c = tid; c < Rprod; c += NT)
+      urow[c] = ordered_sum<16>(
+          0.0, gs->S, [&](int q) { return up[(long long)q * stride + c]; }, [](int, double x) { return x; });
+  }
+  for (int e = tid; e < n * MAXP; e += NT) {
+    const int t = e / MAXP, p = e - t * MAXP;
+    const int R = gs->R[t];
+    int r = 0;
+    while (r + 1 < R && (r + 1) * R - (r + 1) * r / 2 <= p) ++r;
+    const int rr = min(R - 1, r + (p - (r * R - r * (r - 1) / 2)));
+    pr[e] = r | (rr << 8);
+  }
+  __syncthreads();
+  for (int e = tid; e < n * MAXP; e += NT) {
+    const int t = e / MAXP, p = e - t * MAXP;
+    const int rp = pr[e], r = rp & 255, rr = rp >> 8;
+    mg[e] = p < gs->np[t] ? (r == rr ? 1.0 : 2.0) * g[t * MAXR + r] * g[t * MAXR + rr] : 0.0;
+  }
+  __syncthreads();
+
+  for (int t = 0; t < n; ++t) {
+    const int R = gs->R[t];
+    // H_j(p_t) over Gamma_k and b_j(r_t) over the U row: the other modes
+    // contracted one at a time, both chains in the same phases
+    const double* hin = gam;
+    const double* bin = urow;
+    for (int c = 0; c < n - 1; ++c) {
+      const int uh = gs->ord[t][c], ub = gs->bord[t][c];
+      double* hout = (c & 1) ? h2 : h1;
+      double* bout = (c & 1) ? b2 : b1;
+      chain_stage(hin, hout, tab + gs->hoff[t][c], gs->hnout[t][c], mg + uh * MAXP, gs->np[uh], gs->hsc[t][c], tid);
+      chain_stage(bin, bout, tab + gs->boff[t][c], gs->bnout[t][c], g + ub * MAXR, gs->R[ub], gs->bsc[t][c], tid);
+      hin = hout;
+      bin = bout;
+      __syncthreads();
+    }
+    if (tid == 0) {
+      // (H + rho I) g = b by L D L^T on one lane; the solve writes the new
+      // column (into the own-side columns) and its pair weights, for the
+      // later sub-blocks
+      double* gt = g + t * MAXR;
+      double* mt = mg + t * MAXP;
+      for (int p = 0; p < gs->np[t]; ++p) Hs[p] = hin[p];
+      for (int r = 0; r < R; ++r) {
+        gold[r] = gt[r];
+        bs[r] = bin[r] + gs->rho * gt[r];
+      }
+      double dg = 0.0;
+      switch (R) {
+        case 1: dg = ldlt_solve_pairs<1>(Hs, bs, gs->rho, gold, gt, mt); break;
+        case 2: dg = ldlt_solve_pairs<2>(Hs, bs, gs->rho, gold, gt, mt); break;
+        case 3: dg = ldlt_solve_pairs<3>(Hs, bs, gs->rho, gold, gt, mt); break;
+        case 4: dg = ldlt_solve_pairs<4>(Hs, bs, gs->rho, gold, gt, mt); break;
+        case 5: dg = ldlt_solve_pairs<5>(Hs, bs, gs->rho, gold, gt, mt); break;
+        case 6: dg = ldlt_solve_pairs<6>(Hs, bs, gs->rho, gold, gt, mt); break;
+        case 7: dg = ldlt_solve_pairs<7>(Hs, bs, gs->rho, gold, gt, mt); break;
+        default: dg = ldlt_solve_pairs<8>(Hs, bs, gs->rho, gold, gt, mt); break;
+      }
+      gs->dgpart[(long long)t * Ik + j] = dg;
+    }
+    __syncthreads();
+    if (tid < R) G[gs->goff_ki[t] + (long long)tid * Ik + j] = g[t * MAXR + tid];
+  }
+  // rows j of every W_{k,m} from the block's new columns
+  for (int t = 0; t < n; ++t) {
+    const int R = gs->R[t], I = gs->dim[t];
+    const double* Gik = gl ? gik + gs->gik_off[t] : G + gs->goff_ik[t];
+    for (int y = tid; y < I; y += NT) {
+      double sum = 0.0;
+      for (int r = 0; r < R; ++r) sum += g[t * MAXR + r] * Gik[(long long)r * I + y];
+      const long long ad = gs->w_off[t] + (long long)j * gs->w_sj[t] + (long long)y * gs->w_sy[t];
+      gs->W64[ad] = sum;
+      Wc[ad] = (TC)sum;
+    }
   }
 }
 
@@ -879,6 +1089,43 @@ hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s) {
     IFCTN_GO(k_solve<float>, dim3((unsigned)a.Ik), dim3(NT), smem, s, a);
   else
     IFCTN_GO(k_solve<double>, dim3((unsigned)a.Ik), dim3(NT), smem, s, a);
+  return hipGetLastError();
+}
+
+// dynamic LDS above 64 KB needs the kernel's limit raised to at least the
+// request (gfx950 has 160 KB of LDS per compute unit, static LDS included);
+// *limit keeps the largest limit set so far for the kernel
+template <typename K>
+static hipError_t allow_large_lds(K kern, int bytes, std::atomic<int>* limit) {
+  int cur = limit->load(std::memory_order_acquire);
+  if (bytes <= cur) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+  if (e == hipSuccess)
+    while (cur < bytes && !limit->compare_exchange_weak(cur, bytes)) {
+    }
+  return e;
+}
+
+hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* stop, hipStream_t s) {
+  static std::atomic<int> big{64 << 10};
+  {
+    const hipError_t e = allow_large_lds(k_gamma, hp.smem, &big);
+    if (e != hipSuccess) return e;
+  }
+  IFCTN_GO(k_gamma, dim3((unsigned)(hp.nw + hp.nuw)), dim3(NT), (size_t)hp.smem, s, gm, stop);
+  return hipGetLastError();
+}
+
+hipError_t launch_solve_gamma(int dtype, const GSolve& hs, const GSolve* gs, hipStream_t s) {
+  static std::atomic<int> big32{64 << 10}, big64{64 << 10};
+  const dim3 grid((unsigned)hs.Ik), blk(NT);
+  const hipError_t e = dtype == 0 ? allow_large_lds(k_solve_gamma<float>, hs.smem, &big32)
+                                  : allow_large_lds(k_solve_gamma<double>, hs.smem, &big64);
+  if (e != hipSuccess) return e;
+  if (dtype == 0)
+    IFCTN_GO(k_solve_gamma<float>, grid, blk, (size_t)hs.smem, s, gs);
+  else
+    IFCTN_GO(k_solve_gamma<double>, grid, blk, (size_t)hs.smem, s, gs);
   return hipGetLastError();
 }
 

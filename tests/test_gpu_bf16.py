@@ -147,23 +147,25 @@ def test_bf16_refine_msi256_full_size():
     assert rse <= 1.01 * rse32
 
 
-@pytest.mark.parametrize("dims,R", [((14, 12, 9, 11), 3), ((9, 8, 7, 6, 8), 2), ((6, 7, 5, 6, 5), 4)])
-def test_bf16_refine_orders_4_5_match_oracle(dims, R):
-    """Several bfloat16 sweeps and then float32 refinement sweeps at orders 4
-    and 5 (the served mix runs this precision on such tensors): 15 + 15
-    sweeps against 30 oracle sweeps.  These small random tensors are still
-    moving fast at sweep 30, so half of the sweeps refine in float32 (with a
-    third, the order-4 case measured 1.2e-3)."""
+@pytest.mark.parametrize("dims,R,keep", [((14, 12, 9, 11), 3, 0.3), ((9, 8, 7, 6, 8), 2, 0.3),
+                                         ((6, 7, 5, 6, 5), 4, 0.3), ((20, 16, 12, 10), 5, 0.1)])
+def test_bf16_refine_orders_4_5_match_oracle(dims, R, keep):
+    """Bfloat16 sweeps, then float32 refinement sweeps, at orders 4 and 5 on
+    requests drawn like the served mix (planted iFCTN with N(0, 1) factors,
+    unit max, N(0, 0.01^2) noise, Bernoulli sampling): 40 + 20 sweeps
+    against 60 oracle sweeps (the served mix refines the last 30 of 100)."""
     from paper_2511_16358_amd import ifctn
-    p = W.random_problem(dims, W.uniform_ranks(len(dims), R), seed=61 + R, keep=0.4)
+    spec = W.ServedSpec(0, 0.0, tuple(dims), W.uniform_ranks(len(dims), R), keep, 71 + R,
+                        W._draw_factors(np.random.default_rng(70 + R), dims, W.uniform_ranks(len(dims), R), "normal"))
+    p = W.served_problem(spec, oracle.reconstruct(spec.planted, spec.dims))
     print(f"[case] bf16 refine dims={dims} R={R}", flush=True)
     O64 = p.O.astype(np.float64)
-    Xo, _, _ = oracle.pam(O64, p.mask, p.G0, p.dims, rho=p.rho, t_max=30, eps=0.0)
-    X, st = ifctn.complete(p.O, p.mask, p.G0, p.dims, p.ranks, t_max=30, precision=ifctn.IFCTN_BF16_REFINE,
-                           refine_sweeps=15)
+    Xo, _, _ = oracle.pam(O64, p.mask, p.G0, p.dims, rho=p.rho, t_max=60, eps=0.0)
+    X, st = ifctn.complete(p.O, p.mask, p.G0, p.dims, p.ranks, t_max=60, precision=ifctn.IFCTN_BF16_REFINE,
+                           refine_sweeps=20)
     e = relerr(X.cpu().numpy(), Xo)
-    print(f"{dims} R={R}: bf16(15)+fp32(15) vs oracle(30): {e:.2e}")
-    assert st["sweeps_done"] == 30
+    print(f"{dims} R={R}: bf16(40)+fp32(20) vs oracle(60): {e:.2e}")
+    assert st["sweeps_done"] == 60
     assert e < 1e-3
     m = p.mask.astype(bool)
     assert np.array_equal(X.cpu().numpy()[m], p.O[m])

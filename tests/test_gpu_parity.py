@@ -116,10 +116,12 @@ def test_phased_factor_blocks_match_oracle(dims, ranks, precision):
     p = W.random_problem(dims, ranks, seed=17)
     prec = ifctn.IFCTN_FP64 if precision == "fp64" else ifctn.IFCTN_FP32
     ifctn.set_option("phased_min", 0)
+    ifctn.set_option("gamma", 0)
     try:
         r = run_both(p, 3, prec)
     finally:
         ifctn.set_option("phased_min", -1)
+        ifctn.set_option("gamma", -1)
     tol = 1e-10 if precision == "fp64" else 1e-5
     assert_x_close(r["Xg"], r["Xo"], tol)
     for key in r["Go"]:
@@ -171,12 +173,36 @@ def test_phased_one_launch_form_matches_oracle(dims, ranks):
     p = W.random_problem(dims, ranks, seed=29)
     ifctn.set_option("phased_min", 0)
     ifctn.set_option("phased_onelaunch", 1)
+    ifctn.set_option("gamma", 0)
     try:
         r = run_both(p, 3, ifctn.IFCTN_FP64)
     finally:
         ifctn.set_option("phased_min", -1)
         ifctn.set_option("phased_onelaunch", -1)
+        ifctn.set_option("gamma", -1)
     assert_x_close(r["Xg"], r["Xo"], 1e-10)
+
+
+@pytest.mark.parametrize("dims,ranks", SMALL, ids=["x".join(map(str, d)) for d, _ in SMALL])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_gamma_route_matches_oracle(dims, ranks, precision):
+    """Every factor block by the Gamma route (Gamma_k = Z_k^T Z_k built on the
+    matrix cores, per-column H_j from it), three sweeps in one call."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem(dims, ranks, seed=53 + len(dims), keep=0.5)
+    prec = ifctn.IFCTN_FP64 if precision == "fp64" else ifctn.IFCTN_FP32
+    ifctn.set_option("gamma", 2)
+    try:
+        r = run_both(p, 3, prec, batch=3)
+    finally:
+        ifctn.set_option("gamma", -1)
+    tol = 1e-10 if precision == "fp64" else 1e-5
+    assert_x_close(r["Xg"], r["Xo"], tol)
+    for key in r["Go"]:
+        assert relerr(r["Gg"][key], r["Go"][key]) < 10 * tol, key
+    g, o = r["gs"][-1], r["os"][-1]
+    assert abs(g["objective"] - o["objective"]) <= 10 * tol * max(o["objective"], 1e-30)
+    assert abs(g["dg_norm2"] - o["dg_norm2"]) <= 100 * tol * max(o["dg_norm2"], 1e-30)
 
 
 @pytest.mark.parametrize("dims,ranks", SMALL[:5], ids=["x".join(map(str, d)) for d, _ in SMALL[:5]])
@@ -476,17 +502,21 @@ def _random_case(seed):
 @pytest.mark.parametrize("seed", range(16))
 def test_random_shapes_fp64(seed):
     """Random orders 2-5, mode sizes 1-13 and unequal edge ranks 1-8: two
-    FP64 sweeps against the oracle (every other case with the phased factor
-    blocks forced)."""
+    FP64 sweeps against the oracle (a third of the cases with the phased
+    per-column form forced, a third with the Gamma route forced)."""
     from paper_2511_16358_amd import ifctn
     dims, ranks = _random_case(seed)
     p = W.random_problem(dims, ranks, seed=seed, keep=0.6)
-    if seed % 2:
+    if seed % 3 == 1:          # per-column route, phased form
         ifctn.set_option("phased_min", 0)
+        ifctn.set_option("gamma", 0)
+    elif seed % 3 == 2:        # Gamma route wherever it fits
+        ifctn.set_option("gamma", 2)
     try:
         r = run_both(p, 2, ifctn.IFCTN_FP64)
     finally:
         ifctn.set_option("phased_min", -1)
+        ifctn.set_option("gamma", -1)
     assert_x_close(r["Xg"], r["Xo"], 1e-10, (dims, ranks.tolist()))
     for key in r["Go"]:
         assert relerr(r["Gg"][key], r["Go"][key]) < 1e-9, (key, dims)
