@@ -2,12 +2,17 @@
 
 A step is one full PAM sweep (every factor block of eq. (updateG), the
 reconstruction and the X step of eq. (updateX), with the stop-test
-reductions) over the msi256 workload: 256x256x31 multispectral-image-shaped
-tensor, planted iFCTN R=6 + Gaussian bumps + noise, 10% uniform sampling,
-rho = 0.1.  Inputs are resident in HBM before the timed region.
+reductions) over the video144 workload: the largest single-GPU
+configuration, an order-4 144x176x3x50 colour-video-shaped tensor, planted
+iFCTN R=5 + a smoothly translated texture, 5% uniform sampling, rho = 0.1.
+Inputs are resident in HBM before the timed region.
 
 Prints one JSON line with sweeps/s, the roofline of the dominant kernel
-(HIP events on the job's stream) and the CPU oracle baseline.
+class and of every class (HIP events on the job's stream), the precision
+comparison (bfloat16 + float32 refinement against float32 at equal RSE) on
+the image-, traffic- and video-shaped workloads, the served mix, the
+rank-grid tuning batches, a secondary image-shaped (256x256x31) leg and the
+CPU oracle baseline (single thread and all host cores).
 """
 from __future__ import annotations
 
@@ -22,15 +27,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
-
-
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="msi256")
+    ap.add_argument("--workload", default="video144")
+    ap.add_argument("--secondary", default="msi256", help="a second workload timed the same way ('' = none)")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64", "bf16"],
                     help="bf16 = bfloat16 X streaming + float32 refinement sweeps (BF16_REFINE)")
     ap.add_argument("--refine", type=int, default=30, help="float32 refinement sweeps of the bf16 path")
@@ -46,7 +49,9 @@ def parse():
                     help="requests of the mix also run alone, one after another (0 = skip)")
     ap.add_argument("--no-tuning", action="store_true", help="skip the rank-grid tuning leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sweeps", type=int, default=0, help="oracle sweeps (0 = auto, ~10-30 s)")
+    ap.add_argument("--cpu-baseline-only", default=None, metavar="WORKLOAD",
+                    help="only run the CPU oracle baseline on this workload and print its JSON")
+    ap.add_argument("--cpu-seed", type=int, default=0)
     ap.add_argument("--route", default="auto", choices=["auto", "percolumn", "gamma"],
                     help="factor-block route: auto (the library's default), the per-column Gram-weight "
                          "route only, or the Gamma route wherever it fits")
@@ -55,17 +60,21 @@ def parse():
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "contract_msi256_traffic.txt")
+HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFS = 78.6
 
 
 def measured_traffic(workload, precision):
     """HBM bytes per contraction launch from the committed counter summary, or None.
 
-    The summary holds FETCH_SIZE and WRITE_SIZE per dispatch, already scaled by
-    a plain copy of known size; it counts only while the kernel sources are the
-    ones the counters were taken on."""
-    if workload != "msi256" or precision != "fp32" or not os.path.exists(TRAFFIC_FILE):
+    The summary (profiles/contract_<workload>_traffic.txt) holds FETCH_SIZE
+    and WRITE_SIZE per dispatch, already scaled by a plain copy of known size;
+    it counts only while the kernel sources are the ones the counters were
+    taken on."""
+    path = os.path.join(ROOT, "profiles", f"contract_{workload}_traffic.txt")
+    if precision != "fp32" or not os.path.exists(path):
         return None
+    TRAFFIC_FILE = path
     rec = {}
     with open(TRAFFIC_FILE) as f:
         for line in f:
@@ -111,35 +120,83 @@ def contraction_bytes(n_con, n_fused, read, upd):
     return (n_con - n_fused) * read + n_fused * upd
 
 
-def cpu_baseline(name, seed, sweeps_req):
-    """The FP64 oracle (single thread) on a bounded sample of the workload."""
+_FORK_FN = None
+
+
+def _fork_call(item):
+    return _FORK_FN(item)
+
+
+def fork_map(nproc):
+    """A map over the columns of one factor block on nproc forked worker
+    processes (they inherit the block's operands; only the solved columns
+    travel back).  Timing wrapper only: the oracle's arithmetic is unchanged."""
+    import multiprocessing as mp
+    ctx = mp.get_context("fork")
+
+    def m(fn, items):
+        global _FORK_FN
+        _FORK_FN = fn
+        items = list(items)
+        with ctx.Pool(min(nproc, max(1, len(items)))) as pool:
+            return pool.map(_fork_call, items, chunksize=max(1, len(items) // (4 * nproc)))
+    return m
+
+
+def cpu_model():
     try:
-        from threadpoolctl import threadpool_limits
-    except Exception:  # pragma: no cover
-        threadpool_limits = None
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(name, seed, budget_s=10.0):
+    """The FP64 oracle as it stands, on a bounded sample of the workload: PAM
+    sweeps single-threaded (numpy/BLAS on one thread), then with its
+    per-column solves mapped over the host's cores by forked processes (at
+    most 16, the CPU share of one GPU on the box).  Runs in a process of its
+    own that never touches the GPU (started by bench.py after the GPU work)."""
+    from threadpoolctl import threadpool_limits
     import oracle
     from paper_2511_16358_amd import workloads as W
     p = W.problem(name, seed, lambda d, r, G: oracle.reconstruct(G, d))
     O64 = p.O.astype(np.float64)
-    ctx = threadpool_limits(limits=1) if threadpool_limits else None
-    if ctx:
-        ctx.__enter__()
-    try:
+    nproc = min(16, len(os.sched_getaffinity(0)))
+
+    def run(map_columns):
         X = oracle.initial_x(O64, p.mask)
         G = {k: v.copy() for k, v in p.G0.items()}
         t0 = time.perf_counter()
-        X, G, _ = oracle.pam_sweep(X, G, O64, p.mask, p.dims, p.rho)
-        t1 = time.perf_counter()
-        n = sweeps_req or max(1, min(40, int(15.0 / max(t1 - t0, 1e-3))))
-        for _ in range(n - 1):
-            X, G, _ = oracle.pam_sweep(X, G, O64, p.mask, p.dims, p.rho)
-        dt = time.perf_counter() - t0
-    finally:
-        if ctx:
-            ctx.__exit__(None, None, None)
-    return {"value": n / dt, "unit": "sweeps/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n} PAM sweeps of {name} (same workload, seed {seed}), float64 numpy, "
-                      f"single thread, {dt:.1f} s"}
+        n = 0
+        while n == 0 or (time.perf_counter() - t0 < budget_s and n < 40):
+            X, G, _ = oracle.pam_sweep(X, G, O64, p.mask, p.dims, p.rho, map_columns=map_columns)
+            n += 1
+        return n, time.perf_counter() - t0
+
+    with threadpool_limits(limits=1):
+        n1, t1 = run(map)
+        nn, tn = run(fork_map(nproc))
+    return {"value": round(nn / tn, 3), "unit": "sweeps/s", "cores": nproc, "kind": "oracle",
+            "sample": f"{nn} PAM sweeps of {name} (same workload, seed {seed}), float64 numpy, per-column "
+                      f"solves on {nproc} processes, {tn:.1f} s; single thread: {n1} sweeps in {t1:.1f} s",
+            "single_thread": {"value": round(n1 / t1, 3), "unit": "sweeps/s", "cores": 1,
+                              "sample": f"{n1} sweeps, {t1:.1f} s"},
+            "nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu_model": cpu_model()}
+
+
+def cpu_baseline_child(name, seed):
+    """cpu_baseline in a child process (the oracle never runs in the process
+    that holds the GPU); returns its JSON result."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-baseline-only", name, "--cpu-seed",
+                        str(seed)], capture_output=True, text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def timed_run(ifctn, torch, p, precision, steps, warmup, refine=0):
@@ -332,8 +389,122 @@ def tuning(ifctn, torch):
     return out
 
 
+def load_workload(ifctn, W, name):
+    """Synthetic input of a workload, its planted part assembled by the library."""
+    d = W.draw(name, 0)
+    core = ifctn.assemble(d.dims, d.ranks, d.planted, precision=ifctn.IFCTN_FP64).cpu().numpy()
+    return W.finish(d, core)
+
+
+def time_sweeps(ifctn, torch, p, prec, steps, warmup):
+    """Warm-up, then exactly `steps` sweeps timed with events on the job's
+    stream; then the same count again with per-kernel events.  Returns the
+    timing, the per-class figures, the statistics and the job."""
+    Oin = p.O.astype(np.float64) if prec == ifctn.IFCTN_FP64 else p.O
+    job = ifctn.Job(Oin, p.mask, p.G0, p.dims, p.ranks, rho=p.rho, precision=prec)
+    stream = torch.cuda.current_stream()
+    job.sweep(warmup, stats=True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    job.sweep(steps, stats=False)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    st = job.sweep(0, stats=True)
+    job.timing(True)
+    job.sweep(steps, stats=False)
+    per = {}
+    for name, kc in (("contract", ifctn.KC_CONTRACT), ("solve", ifctn.KC_SOLVE),
+                     ("update", ifctn.KC_UPDATE), ("gram", ifctn.KC_GRAM)):
+        ms, n = job.timing_query(kc)
+        per[name] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / max(n, 1)}
+    job.timing(False)
+    return gpu_ms, wall, per, st, job
+
+
+def empty_launch_us(torch, n=64):
+    """Average duration of a one-element fill kernel with events on the
+    current stream: the floor of one dependent launch."""
+    x = torch.zeros(1, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(8):
+        x.fill_(1.0)
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(n)]
+    for a, b in ev:
+        a.record(stream)
+        x.fill_(2.0)
+        b.record(stream)
+    torch.cuda.synchronize()
+    return sum(a.elapsed_time(b) for a, b in ev) / n * 1e3
+
+
+def rooflines(ifctn, p, per, steps, esz, empty_us):
+    """Roofline of every kernel class of the sweep (see the design notes):
+    contraction -- HBM bytes (N reads of X per sweep, the fused X step on
+    mode 0) against 8 TB/s; Gamma build -- FP64 multiply-adds of Gamma_k on
+    the matrix cores against 78.6 TFLOP/s; solve -- a chain of N - 1
+    dependent sub-block steps per launch, FP64 flops against 78.6 TFLOP/s
+    and microseconds per step above the empty-launch floor."""
+    mask_frac = float(p.mask.mean())
+    nX, rd, upd = algorithmic_bytes(p.dims, esz, mask_frac)
+    N = len(p.dims)
+    out = {}
+    n_con = per["contract"]["launches"]
+    if n_con:
+        con_bytes = contraction_bytes(n_con, max(0, steps - 1), rd, upd)
+        gbs = con_bytes / (per["contract"]["total_ms"] * 1e-3) / 1e9
+        out["contract"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                           "algorithmic_bytes_per_launch": round(con_bytes / n_con),
+                           "kernel": "k_contract_rows / k_contract_cols (mode-k contraction, fused X step on mode 0)",
+                           "avg_us": round(per["contract"]["avg_us"], 2)}
+    plan = ifctn.plan_blocks(p.dims, p.ranks)
+    g_fma = sum(f for r, f in plan if r == ifctn.ROUTE_GAMMA)
+    if per["gram"]["launches"] and g_fma > 0:
+        flops = 2.0 * g_fma * steps
+        tfs = flops / (per["gram"]["total_ms"] * 1e-3) / 1e12
+        out["gram"] = {"bound": "mfma", "achieved": round(tfs, 4), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                       "frac": round(tfs / FP64_MFMA_PEAK_TFS, 5), "traffic": None,
+                       "algorithmic_flops_per_launch": round(flops / per["gram"]["launches"]),
+                       "kernel": "k_gamma (Gamma_k = Z_k^T Z_k, v_mfma_f64_16x16x4f64; U rows)",
+                       "avg_us": round(per["gram"]["avg_us"], 2)}
+    if per["solve"]["launches"]:
+        # per column and sub-block: the H and b contraction chains and the
+        # LDL^T; per sub-block: the column count of its block
+        fl = 0.0
+        for k in range(N):
+            Ik = p.dims[k]
+            for i in range(N):
+                if i == k:
+                    continue
+                R = int(p.ranks[k][i])
+                fl += Ik * (2.0 * R ** 3 / 3.0 + 2.0 * R * R)
+            if plan[k][0] == ifctn.ROUTE_GAMMA:
+                npk = [int(p.ranks[k][m]) * (int(p.ranks[k][m]) + 1) // 2 for m in range(N) if m != k]
+                P = int(np.prod(npk))
+                Rp = int(np.prod([int(p.ranks[k][m]) for m in range(N) if m != k]))
+                fl += (N - 1) * Ik * 2.0 * (P + Rp)
+        flops = fl * steps
+        tfs = flops / (per["solve"]["total_ms"] * 1e-3) / 1e12
+        avg = per["solve"]["avg_us"]
+        out["solve"] = {"bound": "alu", "achieved": round(tfs, 5), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
+                        "frac": round(tfs / FP64_MFMA_PEAK_TFS, 6), "traffic": None,
+                        "latency": {"avg_us": round(avg, 2), "dependent_steps_per_launch": N - 1,
+                                    "empty_launch_us": round(empty_us, 2),
+                                    "us_per_step_above_floor": round((avg - empty_us) / (N - 1), 2)},
+                        "kernel": "k_solve_gamma / k_solve (per-column proximal LS, Gauss-Seidel over i)",
+                        "avg_us": round(avg, 2)}
+    return out
+
+
 def main():
     args = parse()
+    if args.cpu_baseline_only:
+        print(json.dumps(cpu_baseline(args.cpu_baseline_only, args.cpu_seed)), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
               f"(one job's sweep runs on one GPU; the multi-GPU mode for these workloads is "
@@ -353,71 +524,48 @@ def main():
     prec = {"fp32": ifctn.IFCTN_FP32, "fp64": ifctn.IFCTN_FP64, "bf16": ifctn.IFCTN_BF16_REFINE}[args.precision]
     esz = {"fp32": 4, "fp64": 8, "bf16": 2}[args.precision]
 
-    # synthetic input: planted part assembled by the library itself
-    d = W.draw(args.workload, 0)
-    core = ifctn.assemble(d.dims, d.ranks, d.planted, precision=ifctn.IFCTN_FP64).cpu().numpy()
-    p = W.finish(d, core)
-    Oin = p.O.astype(np.float64) if prec == ifctn.IFCTN_FP64 else p.O
-    job = ifctn.Job(Oin, p.mask, p.G0, p.dims, p.ranks, rho=p.rho, precision=prec)
-    stream = torch.cuda.current_stream()
-
-    job.sweep(args.warmup, stats=True)
-    torch.cuda.synchronize()
-
-    # timed region: exactly K sweeps
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    ev0.record(stream)
-    job.sweep(args.steps, stats=False)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    gpu_ms = ev0.elapsed_time(ev1)
+    p = load_workload(ifctn, W, args.workload)
+    gpu_ms, wall, per, st, job = time_sweeps(ifctn, torch, p, prec, args.steps, args.warmup)
     ms_per_step = gpu_ms / args.steps
     sweeps_per_s = args.steps / (gpu_ms / 1e3)
-    st = job.sweep(0, stats=True)
-
-    # second pass with per-kernel events (same K) for the roofline
-    job.timing(True)
-    job.sweep(args.steps, stats=False)
-    per = {}
-    for name, kc in (("contract", ifctn.KC_CONTRACT), ("solve", ifctn.KC_SOLVE),
-                     ("update", ifctn.KC_UPDATE), ("gram", ifctn.KC_GRAM)):
-        ms, n = job.timing_query(kc)
-        per[name] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / max(n, 1)}
-    job.timing(False)
-
-    mask_frac = float(p.mask.mean())
-    nX, rd, upd = algorithmic_bytes(p.dims, esz, mask_frac)
-    # contraction launches: N per sweep; the first of each sweep after the
-    # first also carries the previous sweep's X step
-    N = len(p.dims)
-    n_con = per["contract"]["launches"]
-    n_fused = max(0, args.steps - 1)
-    con_bytes = contraction_bytes(n_con, n_fused, rd, upd)
-    dominant = max(per, key=lambda k: per[k]["total_ms"])
-    con_gbs = con_bytes / (per["contract"]["total_ms"] * 1e-3) / 1e9
+    empty_us = empty_launch_us(torch)
+    classes = rooflines(ifctn, p, per, args.steps, esz, empty_us)
     traffic = measured_traffic(args.workload, args.precision)
-    roof = {"bound": "hbm", "achieved": round(con_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(con_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None if traffic is None else round(traffic),
-            "algorithmic_bytes_per_launch": round(con_bytes / max(n_con, 1)),
-            "kernel": "k_contract (mode-k contraction, fused X step on mode 0)",
-            "avg_us": round(per["contract"]["avg_us"], 2)}
-
+    if traffic is not None and "contract" in classes:
+        classes["contract"]["traffic"] = round(traffic)
+    dominant = max((k for k in per if k in classes), key=lambda k: per[k]["total_ms"])
+    roof = dict(classes[dominant])
     Xdev = job.x()
     Xf = Xdev.cpu().numpy().astype(np.float64)
     rse = float(np.linalg.norm((Xf - p.X_true).ravel()) / np.linalg.norm(p.X_true.astype(np.float64).ravel()))
-    image = None
-    if len(p.dims) == 3 and args.workload == "msi256":
-        mp, ms, _, _ = ifctn.image_metrics(Xdev.float(), p.X_true)
-        image = {"mpsnr_db": round(mp, 3), "mssim": round(ms, 4)}
     job.close()
+
+    secondary = None
+    if args.secondary:
+        p2 = load_workload(ifctn, W, args.secondary)
+        ms2, _, per2, _, job2 = time_sweeps(ifctn, torch, p2, prec, args.steps, args.warmup)
+        Xd2 = job2.x()
+        image = None
+        if len(p2.dims) == 3 and args.secondary == "msi256":
+            mp, mss, _, _ = ifctn.image_metrics(Xd2.float(), p2.X_true)
+            image = {"mpsnr_db": round(mp, 3), "mssim": round(mss, 4)}
+        job2.close()
+        c2 = rooflines(ifctn, p2, per2, args.steps, esz, empty_us)
+        t2 = measured_traffic(args.secondary, args.precision)
+        if t2 is not None and "contract" in c2:
+            c2["contract"]["traffic"] = round(t2)
+        secondary = {"workload": f"{args.secondary}: {W.DESCRIPTIONS[args.secondary]}",
+                     "value": round(args.steps / (ms2 / 1e3), 2), "unit": "sweeps/s",
+                     "ms_per_step": round(ms2 / args.steps, 5), "roofline_classes": c2,
+                     "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per2.items()},
+                     "image_metrics_after_timed_sweeps": image}
 
     cmp = None
     if not args.no_compare and args.precision != "fp64":
-        cmp = precision_comparison(ifctn, torch, p, W.CONFIGS[args.workload][2], args.refine)
+        cmp = {}
+        for name in ("video144", "traffic214", "msi256"):
+            pc = p if name == args.workload else load_workload(ifctn, W, name)
+            cmp[name] = precision_comparison(ifctn, torch, pc, W.CONFIGS[name][2], args.refine)
 
     served = None
     if not args.no_serve:
@@ -429,7 +577,7 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(args.workload, 0, args.cpu_sweeps)
+        cpu = cpu_baseline_child(args.workload, 0)
 
     out = {
         "metric": "PAM sweeps/sec",
@@ -448,16 +596,18 @@ def main():
                    "dims": list(p.dims), "rank": int(p.ranks[0][1]), "rho": p.rho,
                    "precision": f"{args.precision} X streaming ({'float64' if args.precision == 'fp64' else 'float32'} arithmetic), "
                                 "fp64 Gram/LDL^T/factors/reductions",
+                   "routes": [["per-column", "phased", "gamma"][r] for r, _ in ifctn.plan_blocks(p.dims, p.ranks)],
                    "parallelism": "single GPU"},
         "roofline": roof,
+        "roofline_classes": classes,
+        "dominant_kernel_class": dominant,
         "cpu_baseline": cpu,
         "precision_comparison": cmp,
+        "secondary": secondary,
         "serving": served,
         "tuning": tune,
         "kernels": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in per.items()},
-        "dominant_kernel_class": dominant,
         "rse_after_timed_sweeps": rse,
-        "image_metrics_after_timed_sweeps": image,
         "objective": st["objective"],
         "wall_s_timed": round(wall, 4),
     }

@@ -237,6 +237,21 @@ ifctn_status ifctn_image_metrics(const void* X_dev, const void* ref_dev, int64_t
                                  int32_t precision, double peak, double* psnr_host, double* ssim_host,
                                  double* mpsnr, double* mssim, void* stream);
 
+/* How each factor block of a job with these params would run (with the
+ * options as they stand), one entry per mode k in out[0 .. order-1]:
+ *   route: 0 = per-column solves with the Gram weights of eq. (updateG)
+ *          computed in the contraction launch; 1 = the same in the phased
+ *          form; 2 = the Gamma route (Gamma_k = Z_k^T Z_k of Prop. 1 built in
+ *          a launch of its own, per-column H_j from it);
+ *   gamma_fma: route 2 only, multiply-adds of building Gamma_k.
+ * IFCTN_E_INVAL for invalid params or a NULL out. */
+typedef struct {
+  int32_t route;
+  int32_t reserved;
+  double gamma_fma;
+} ifctn_block_plan;
+ifctn_status ifctn_plan_blocks(const ifctn_params* params, ifctn_block_plan* out);
+
 /* Process-wide tuning option, read when a job is created:
  *   "phased_min": a factor block uses the phased form (partial Gram matrices
  *   over ranges of the Gram weight set on many workgroups, then one
@@ -258,6 +273,12 @@ ifctn_status ifctn_image_metrics(const void* X_dev, const void* ref_dev, int64_t
  *   <= 0 restore it).
  * Unknown names: IFCTN_E_INVAL. */
 ifctn_status ifctn_set_option(const char* name, int64_t value);
+/*   "gamma": factor-block route -- 1 (default): the Gamma route for blocks
+ *   that would otherwise take the phased form, 0: never, 2: wherever it fits.
+ *   "ugroup": the contraction's partial slots are summed in groups of this
+ *   many by the last workgroup of each group (default 0: off).
+ *   "inject_admit_failures": the next `value` server admissions fail with
+ *   IFCTN_E_NOMEM (fault injection for tests). */
 
 /* Message of the last failed call on this thread ("" if none). */
 const char* ifctn_last_error(void);

@@ -145,16 +145,22 @@ def _axis_vector(v, axis, N):
     return v.reshape(shape)
 
 
-def update_factor(X, G, dims, k, i, rho):
+def update_factor(X, G, dims, k, i, rho, map_columns=map):
     """Solve eq. (updateG) for every column j of G_{k,i} (columns are
     independent: y_j, D and G_{i,k} do not involve G_{k,i}).  The SPD system
-    (H_j, b_j) is solved by a Cholesky factorisation."""
+    (H_j, b_j) is solved by a Cholesky factorisation.  ``map_columns`` maps
+    the per-column solve over the columns (the built-in ``map`` by default; a
+    thread pool's map runs the same arithmetic on several cores)."""
     ops = block_operands(G, dims, k, i)
-    Gnew = G[(k, i)].copy()
-    for j in range(dims[k]):
+
+    def solve(j):
         _, _, H, b = column_system(X, G, dims, k, i, j, rho, operands=ops)
         c = scipy.linalg.cho_factor(H, lower=True)
-        Gnew[:, j] = scipy.linalg.cho_solve(c, b)
+        return scipy.linalg.cho_solve(c, b)
+
+    Gnew = G[(k, i)].copy()
+    for j, g in enumerate(map_columns(solve, range(dims[k]))):
+        Gnew[:, j] = g
     return Gnew
 
 
@@ -245,14 +251,14 @@ def block_order(N):
     return [(k, i) for k in range(N) for i in range(N) if i != k]
 
 
-def pam_sweep(X, G, O, mask, dims, rho, rho_x=None):
+def pam_sweep(X, G, O, mask, dims, rho, rho_x=None, map_columns=map):
     """One iteration of Algorithm 1.  Returns (X_new, G_new, stats)."""
     if rho_x is None:
         rho_x = rho
     G = {key: v.copy() for key, v in G.items()}
     dg2 = 0.0
     for k, i in block_order(len(dims)):
-        new = update_factor(X, G, dims, k, i, rho)
+        new = update_factor(X, G, dims, k, i, rho, map_columns)
         dg2 += float(np.sum((new - G[(k, i)]) ** 2))
         G[(k, i)] = new
     Xhat = reconstruct(G, dims)

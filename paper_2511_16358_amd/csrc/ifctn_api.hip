@@ -630,6 +630,7 @@ bool plan_gamma(const Geo& g, int k, GammaPlan* gp) {
   const double costA = n >= 2 ? (gp->hasx ? (double)gp->dim[px] : 1.0) * gp->dim[py] * gp->np[py] : 0.0;
   const double costB = gp->hasx ? (double)gp->dim[px] * gp->np[px] * gp->np[py] : 0.0;
   const double total = (double)gp->nq * (costA + costB + (double)P);
+  gp->fma = total;
   long long nwt = (long long)std::ceil(total / 32768.0);
   nwt = std::max<long long>(1, std::min<long long>(nwt, GM_MAXW));
   int nyg = (int)std::min<long long>(npy, nwt);
@@ -1643,6 +1644,26 @@ ifctn_status ifctn_assemble(const ifctn_params* params, const double* G_host, vo
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   (void)hipFree(buf);
   if (e != hipSuccess) return fail(IFCTN_E_HIP, "assemble: %s", hipGetErrorString(e));
+  return IFCTN_OK;
+}
+
+ifctn_status ifctn_plan_blocks(const ifctn_params* params, ifctn_block_plan* out) {
+  if (!out) return fail(IFCTN_E_INVAL, "out is NULL");
+  Geo g;
+  ifctn_status st = make_geo(params, &g);
+  if (st != IFCTN_OK) return st;
+  const PlanOpts o = current_opts();
+  ContractPlan cp[MAXN];
+  QArgs qp[MAXN];
+  GammaPlan gp[MAXN];
+  GSolve gs[MAXN];
+  bool gr[MAXN] = {};
+  job_sizes(g, cp, qp, o, gp, gs, gr);
+  for (int k = 0; k < g.N; ++k) {
+    out[k].route = gr[k] ? 2 : (use_phased(g, qp[k], k, o) ? 1 : 0);
+    out[k].reserved = 0;
+    out[k].gamma_fma = gr[k] ? gp[k].fma : 0.0;
+  }
   return IFCTN_OK;
 }
 

@@ -104,6 +104,7 @@ struct GammaPlan {
   // the nqg partial sums of a y group are added by its last workgroup
   int nyg, pyw, nqg;
   int nw;                       // nyg * nqg
+  double fma;                   // multiply-adds of the build (stage A + B + accumulation)
   int smem;                     // LDS bytes of a workgroup
   // LDS offsets (doubles)
   int o_gy, o_gx, o_wa, o_cq, o_wb, o_t, o_y, o_cp, o_pr;

@@ -34,7 +34,12 @@ EXPORTED = [
     "ifctn_assemble", "ifctn_timing_enable", "ifctn_timing_query", "ifctn_last_error",
     "ifctn_promote", "ifctn_server_create", "ifctn_server_submit", "ifctn_server_poll",
     "ifctn_server_queued", "ifctn_server_destroy", "ifctn_set_option", "ifctn_image_metrics",
+    "ifctn_plan_blocks",
 ]
+
+
+class IfctnBlockPlan(ctypes.Structure):
+    _fields_ = [("route", ctypes.c_int32), ("reserved", ctypes.c_int32), ("gamma_fma", ctypes.c_double)]
 
 
 class IfctnParams(ctypes.Structure):
@@ -137,6 +142,7 @@ def lib():
         "ifctn_server_queued": (st, [vp, ctypes.POINTER(i32), ctypes.POINTER(i32)]),
         "ifctn_server_destroy": (st, [vp]),
         "ifctn_set_option": (st, [ctypes.c_char_p, ctypes.c_int64]),
+        "ifctn_plan_blocks": (st, [P, ctypes.POINTER(IfctnBlockPlan)]),
         "ifctn_image_metrics": (st, [vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, i32, ctypes.c_double,
                                      dp, dp, dp, dp, vp]),
     }
@@ -176,6 +182,16 @@ def _dptr(arr: np.ndarray):
 
 def num_factor_entries(dims, ranks) -> int:
     return int(lib().ifctn_num_factor_entries(ctypes.byref(make_params(dims, ranks))))
+
+
+ROUTE_PERCOLUMN, ROUTE_PHASED, ROUTE_GAMMA = 0, 1, 2
+
+
+def plan_blocks(dims, ranks, precision=IFCTN_FP32):
+    """Per mode k: (route, multiply-adds of building Gamma_k) (ifctn_plan_blocks)."""
+    out = (IfctnBlockPlan * IFCTN_MAX_ORDER)()
+    _check(lib().ifctn_plan_blocks(ctypes.byref(make_params(tuple(dims), ranks, precision=precision)), out))
+    return [(int(out[k].route), float(out[k].gamma_fma)) for k in range(len(dims))]
 
 
 def workspace_bytes(dims, ranks, precision=IFCTN_FP32) -> int:

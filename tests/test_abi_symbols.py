@@ -68,6 +68,7 @@ def test_struct_layouts_match_header(tmp_path):
         "ifctn_request": ("IfctnRequest", ["params", "O_dev", "mask_dev", "G0_host", "t_max", "eps",
                                            "X_out_dev", "tag"]),
         "ifctn_completion": ("IfctnCompletion", ["tag", "status", "stats", "t_submit", "t_admit", "t_done"]),
+        "ifctn_block_plan": ("IfctnBlockPlan", ["route", "reserved", "gamma_fma"]),
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ifctn.h"', "int main(void) {"]
     for cname, (_, fl) in fields.items():
