@@ -192,7 +192,7 @@ def _mut_params_counts_edges_once(m):
 
 
 def _mut_cholesky_upper_misuse(m):
-    def update_factor(X, G, dims, k, i, rho):
+    def update_factor(X, G, dims, k, i, rho, map_columns=map):
         ops = m.block_operands(G, dims, k, i)
         Gnew = G[(k, i)].copy()
         for j in range(dims[k]):
