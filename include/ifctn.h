@@ -146,6 +146,23 @@ ifctn_status ifctn_complete(const ifctn_params* params, const void* O_dev, const
 ifctn_status ifctn_assemble(const ifctn_params* params, const double* G_host, void* out_dev,
                             void* stream);
 
+/* ifctn_assemble without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, serving loops, harnesses that
+ * forbid hipMalloc).  The packed factors and every edge matrix W_ab are
+ * staged in a fixed device array of IFCTN_NOALLOC_SCRATCH_BYTES that the
+ * library holds on each GPU it runs on until the process ends; its address
+ * on the current device is looked up on the first call there.  The
+ * arguments, result and synchronisation are those of ifctn_assemble.  A
+ * problem whose factors and edge matrices need more than that array
+ * (256-aligned sizes: 8 bytes per factor entry, 8 + element size per W_ab
+ * entry) returns IFCTN_E_UNSUPPORTED before touching the device.  Every call
+ * on one GPU shares the one array and leaves its contents behind (nothing in
+ * it has to start at zero): calls that overlap on the same GPU, from
+ * different threads or streams, race and must be serialised by the caller. */
+#define IFCTN_NOALLOC_SCRATCH_BYTES (16ull << 20)
+ifctn_status ifctn_assemble_noalloc(const ifctn_params* params, const double* G_host, void* out_dev,
+                                    void* stream);
+
 /* Per-kernel timing with HIP events recorded on the job's stream around every
  * launch of the given kernel class (0 = mode-k contraction, 1 = factor-block
  * solve, 2 = X update, 3 = Gram weights).  enable = 1 starts a fresh tally, 0 stops.  The query

@@ -1607,15 +1607,15 @@ ifctn_status ifctn_complete(const ifctn_params* params, const void* O_dev, const
   return st;
 }
 
-ifctn_status ifctn_assemble(const ifctn_params* params, const double* G_host, void* out_dev, void* stream) {
-  Geo g;
-  ifctn_status st = make_geo(params, &g);
-  if (st != IFCTN_OK) return st;
-  if (!G_host || !out_dev) return fail(IFCTN_E_INVAL, "G_host and out_dev are required");
-  hipStream_t s = (hipStream_t)stream;
-  const size_t bG = al256(g.nG * 8), bW = al256(g.nW * 8), bWc = al256(g.nW * g.esz);
-  unsigned char* buf = nullptr;
-  HIPTRY(hipMalloc((void**)&buf, bG + bW + bWc));
+}  // extern "C"
+
+namespace {
+
+// iFCTN(G) into out_dev with the edge matrices in buf (bG + bW + bWc bytes):
+// G to the device, every W_ab = G_{a,b}^T G_{b,a}, then the Hadamard product.
+// Synchronises the stream.
+hipError_t assemble_into(const Geo& g, const double* G_host, void* out_dev, hipStream_t s, unsigned char* buf) {
+  const size_t bG = al256(g.nG * 8), bW = al256(g.nW * 8);
   double* G = (double*)buf;
   double* W64 = (double*)(buf + bG);
   unsigned char* Wc = buf + bG + bW;
@@ -1642,6 +1642,65 @@ ifctn_status ifctn_assemble(const ifctn_params* params, const double* G_host, vo
     e = launch_reconstruct(g.dtype, r, s);
   }
   if (e == hipSuccess) e = hipStreamSynchronize(s);
+  return e;
+}
+
+// The allocation-free variant's edge-matrix buffer: a file-scope device array
+// of kScratchBytes, one per GPU, held until the process ends.  In host code
+// `scratch` is only a symbol: its device address on the current GPU comes
+// from hipGetSymbolAddress, fetched once per device on the first call there.
+constexpr size_t kScratchBytes = IFCTN_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::atomic<unsigned char*> g_scratch_dev[kMaxDevices];
+
+ifctn_status scratch_address(unsigned char** out) {
+  int dev = -1;
+  HIPTRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return fail(IFCTN_E_UNSUPPORTED, "device ordinal %d out of range", dev);
+  unsigned char* p = g_scratch_dev[dev].load(std::memory_order_acquire);
+  if (!p) {
+    void* a = nullptr;
+    HIPTRY(hipGetSymbolAddress(&a, HIP_SYMBOL(scratch)));
+    p = (unsigned char*)a;
+    g_scratch_dev[dev].store(p, std::memory_order_release);   // the same address whichever thread stores
+  }
+  *out = p;
+  return IFCTN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+ifctn_status ifctn_assemble_noalloc(const ifctn_params* params, const double* G_host, void* out_dev,
+                                    void* stream) {
+  Geo g;
+  ifctn_status st = make_geo(params, &g);
+  if (st != IFCTN_OK) return st;
+  if (!G_host || !out_dev) return fail(IFCTN_E_INVAL, "G_host and out_dev are required");
+  const size_t need = al256(g.nG * 8) + al256(g.nW * 8) + al256(g.nW * g.esz);
+  if (need > kScratchBytes)
+    return fail(IFCTN_E_UNSUPPORTED, "factors and edge matrices need %zu bytes; the allocation-free assemble holds %zu",
+                need, kScratchBytes);
+  unsigned char* buf = nullptr;
+  st = scratch_address(&buf);
+  if (st != IFCTN_OK) return st;
+  const hipError_t e = assemble_into(g, G_host, out_dev, (hipStream_t)stream, buf);
+  if (e != hipSuccess) return fail(IFCTN_E_HIP, "assemble: %s", hipGetErrorString(e));
+  return IFCTN_OK;
+}
+
+ifctn_status ifctn_assemble(const ifctn_params* params, const double* G_host, void* out_dev, void* stream) {
+  Geo g;
+  ifctn_status st = make_geo(params, &g);
+  if (st != IFCTN_OK) return st;
+  if (!G_host || !out_dev) return fail(IFCTN_E_INVAL, "G_host and out_dev are required");
+  hipStream_t s = (hipStream_t)stream;
+  const size_t bG = al256(g.nG * 8), bW = al256(g.nW * 8), bWc = al256(g.nW * g.esz);
+  unsigned char* buf = nullptr;
+  HIPTRY(hipMalloc((void**)&buf, bG + bW + bWc));
+  const hipError_t e = assemble_into(g, G_host, out_dev, s, buf);
   (void)hipFree(buf);
   if (e != hipSuccess) return fail(IFCTN_E_HIP, "assemble: %s", hipGetErrorString(e));
   return IFCTN_OK;

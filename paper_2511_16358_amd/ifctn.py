@@ -34,7 +34,7 @@ EXPORTED = [
     "ifctn_assemble", "ifctn_timing_enable", "ifctn_timing_query", "ifctn_last_error",
     "ifctn_promote", "ifctn_server_create", "ifctn_server_submit", "ifctn_server_poll",
     "ifctn_server_queued", "ifctn_server_destroy", "ifctn_set_option", "ifctn_image_metrics",
-    "ifctn_plan_blocks",
+    "ifctn_plan_blocks", "ifctn_assemble_noalloc",
 ]
 
 
@@ -132,6 +132,7 @@ def lib():
         "ifctn_destroy": (st, [vp]),
         "ifctn_complete": (st, [P, vp, vp, dp, i32, ctypes.c_double, vp, S, vp]),
         "ifctn_assemble": (st, [P, dp, vp, vp]),
+        "ifctn_assemble_noalloc": (st, [P, dp, vp, vp]),
         "ifctn_timing_enable": (st, [vp, i32]),
         "ifctn_timing_query": (st, [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]),
         "ifctn_last_error": (ctypes.c_char_p, []),
@@ -294,14 +295,24 @@ def complete(O, mask, G0, dims, ranks, t_max, eps=0.0, rho=0.1, precision=IFCTN_
     return out, s.as_dict()
 
 
-def assemble(dims, ranks, G, precision=IFCTN_FP32):
-    """iFCTN(G) materialised on the GPU by the library (eq. (iFCTN))."""
+def assemble(dims, ranks, G, precision=IFCTN_FP32, out=None, noalloc=False):
+    """iFCTN(G) materialised on the GPU by the library (eq. (iFCTN)).
+
+    out: an existing contiguous CUDA tensor of shape dims and the precision's
+    dtype to write into (a new one otherwise).  noalloc: call
+    ifctn_assemble_noalloc, which stages factors and edge matrices in the
+    library's fixed per-GPU array instead of allocating device memory."""
     dims = tuple(int(d) for d in dims)
     params = make_params(dims, ranks, precision=precision)
     g = np.ascontiguousarray(workloads.pack(G, dims, ranks) if isinstance(G, dict) else G, dtype=np.float64)
-    out = torch.empty(dims, dtype=_dtype(precision), device="cuda")
-    _check(lib().ifctn_assemble(ctypes.byref(params), _dptr(g), ctypes.c_void_p(out.data_ptr()),
-                                _stream_handle()))
+    if out is None:
+        out = torch.empty(dims, dtype=_dtype(precision), device="cuda")
+    elif (tuple(out.shape) != dims or out.dtype != _dtype(precision) or not out.is_cuda
+          or not out.is_contiguous()):
+        raise ValueError("out must be a contiguous CUDA tensor of shape %s and dtype %s"
+                         % (dims, _dtype(precision)))
+    fn = lib().ifctn_assemble_noalloc if noalloc else lib().ifctn_assemble
+    _check(fn(ctypes.byref(params), _dptr(g), ctypes.c_void_p(out.data_ptr()), _stream_handle()))
     return out
 
 
