@@ -41,7 +41,13 @@ extern "C" {
 #endif
 
 #define IFCTN_MAX_ORDER 5 /* tensor order N: 2..5 */
-#define IFCTN_MAX_RANK 8  /* every R[a][b] in 1..8 */
+/* every R[a][b] in 1..36.  A job with all ranks <= 8 runs the fused kernels
+ * (routes 0-2 of ifctn_plan_blocks); a job with any rank above 8 runs every
+ * block by the large-rank route (route 3: X o D_{-k} and its mode products
+ * into U_k, the per-column Gram rows as a GEMM, one Cholesky per column, all
+ * in float64, and a separate X step), in FP32 or FP64 precision only
+ * (BF16_REFINE: IFCTN_E_UNSUPPORTED). */
+#define IFCTN_MAX_RANK 36
 #define IFCTN_MAX_ENTRIES 2147483647LL /* prod(dims) above this: IFCTN_E_UNSUPPORTED */
 
 typedef enum {
@@ -259,7 +265,8 @@ ifctn_status ifctn_image_metrics(const void* X_dev, const void* ref_dev, int64_t
  *   route: 0 = per-column solves with the Gram weights of eq. (updateG)
  *          computed in the contraction launch; 1 = the same in the phased
  *          form; 2 = the Gamma route (Gamma_k = Z_k^T Z_k of Prop. 1 built in
- *          a launch of its own, per-column H_j from it);
+ *          a launch of its own, per-column H_j from it); 3 = the large-rank
+ *          route (every block of a job with an edge rank above 8);
  *   gamma_fma: route 2 only, multiply-adds of building Gamma_k.
  * IFCTN_E_INVAL for invalid params or a NULL out. */
 typedef struct {

@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libifctn.so")
 SOURCES = ["ifctn_api.hip", "ifctn_kernels.hip", "ifctn_contract_f32.hip", "ifctn_contract_f64.hip",
-           "ifctn_contract_bf16.hip", "ifctn_server.hip", "ifctn_metrics.hip"]
+           "ifctn_contract_bf16.hip", "ifctn_server.hip", "ifctn_metrics.hip", "ifctn_large.hip"]
 
 # Packed-FP32 VALU ops are disabled for all device code (-packed-fp32-ops).
 HIPCC_FLAGS = [

@@ -65,6 +65,7 @@ struct Geo {
 };
 
 constexpr long long kMaxEntries = IFCTN_MAX_ENTRIES;
+static_assert(IFCTN_MAX_RANK == LR_MAXR, "the large-rank kernels size their LDS for the largest rank");
 
 ifctn_status make_geo(const ifctn_params* p, Geo* g) {
   if (!p) return fail(IFCTN_E_INVAL, "params is NULL");
@@ -775,6 +776,235 @@ bool plan_gsolve(const Geo& g, int k, const GammaPlan& gp, GSolve* gs, std::vect
 // ---------------------------------------------------------------------------
 // job
 // ---------------------------------------------------------------------------
+size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// ---------------------------------------------------------------------------
+// large-rank route (any edge rank above MAXR): plan of its launches
+// ---------------------------------------------------------------------------
+bool large_ranks(const Geo& g) {
+  for (int a = 0; a < g.N; ++a)
+    for (int b = 0; b < g.N; ++b)
+      if (a != b && g.R[a][b] > MAXR) return true;
+  return false;
+}
+
+// W_uv(x_u, x_v) in the stored edge matrix of {u, v}
+LrEdge lr_edge(const Geo& g, int u, int v) {
+  LrEdge r;
+  r.off = g.woff[g.eid[u][v]];
+  if (u < v) {
+    r.s1 = g.dims[v];
+    r.s2 = 1;
+  } else {
+    r.s1 = 1;
+    r.s2 = g.dims[u];
+  }
+  return r;
+}
+
+struct LrBlock {
+  int nst;
+  LrYArgs y;
+  LrGemmArgs st[MAXN - 1];     // mode products, the last one leaves U_k
+  bool st_out1[MAXN - 1];      // stage output in buffer 1 (else 0)
+  LrCArgs c[MAXN - 1];
+  LrGemmArgs h[MAXN - 1];
+  LrSolveArgs s[MAXN - 1];
+};
+
+struct LrPlan {
+  LrBlock b[MAXN];
+  long long n0 = 0, n1 = 0, nc = 0, nh = 0;   // doubles in buffer 0 / 1, c, H
+  int xblk = 1;
+  LrXArgs x;
+};
+
+// Geometry of every launch (pointers are filled in by lr_bind).  Stage t of
+// block k contracts the last not yet contracted mode m != k, so its input is
+// [A][I_m][B] with the contracted modes (ranks) after m; buffer 0 holds Y,
+// the stages alternate 0 -> 1 -> 0 ...  Returns false when an intermediate
+// exceeds 2^31 entries.
+bool plan_lr(const Geo& g, LrPlan* P) {
+  const int N = g.N;
+  P->n0 = g.nX;
+  for (int k = 0; k < N; ++k) {
+    LrBlock& B = P->b[k];
+    std::memset(&B, 0, sizeof(B));
+    LrYArgs& y = B.y;
+    y.N = N;
+    for (int m = 0; m < N; ++m) y.dims[m] = g.dims[m];
+    y.nX = g.nX;
+    for (int e = 0; e < g.ne; ++e)
+      if (g.ea[e] != k && g.eb[e] != k) {
+        y.ea[y.ne] = g.ea[e];
+        y.eb[y.ne] = g.eb[e];
+        y.woff[y.ne] = g.woff[e];
+        ++y.ne;
+      }
+    long long cur[MAXN];
+    for (int m = 0; m < N; ++m) cur[m] = g.dims[m];
+    int t = 0;
+    for (int m = N - 1; m >= 0; --m) {
+      if (m == k) continue;
+      LrGemmArgs& a = B.st[t];
+      a.A = 1;
+      for (int q = 0; q < m; ++q) a.A *= cur[q];
+      a.Bn = 1;
+      for (int q = m + 1; q < N; ++q) a.Bn *= cur[q];
+      a.I = g.dims[m];
+      a.Nn = g.R[k][m];
+      a.ldb = g.dims[m];
+      cur[m] = g.R[k][m];
+      const long long out = a.A * a.Nn * a.Bn;
+      if (out > (1LL << 31)) return false;
+      B.st_out1[t] = (t % 2) == 0;
+      if (B.st_out1[t])
+        P->n1 = std::max(P->n1, out);
+      else
+        P->n0 = std::max(P->n0, out);
+      ++t;
+    }
+    B.nst = t;
+    long long ustr[MAXN];
+    {
+      long long st = 1;
+      for (int q = N - 1; q >= 0; --q) {
+        ustr[q] = st;
+        st *= cur[q];
+      }
+    }
+    int sb = 0;
+    for (int i = 0; i < N; ++i) {
+      if (i == k) continue;
+      int o[MAXN], nr = 0;
+      for (int m = 0; m < N; ++m)
+        if (m != k && m != i) o[nr++] = m;
+      const int R = g.R[k][i];
+      LrCArgs& c = B.c[sb];
+      c.Ik = g.dims[k];
+      c.Ii = g.dims[i];
+      c.nr = nr;
+      for (int p = 0; p < nr; ++p) {
+        c.rdim[p] = g.dims[o[p]];
+        c.ek[p] = lr_edge(g, k, o[p]);
+        c.ei[p] = lr_edge(g, i, o[p]);
+      }
+      for (int p = 0; p < nr; ++p)
+        for (int q = p + 1; q < nr; ++q) {
+          c.pa[c.npr] = p;
+          c.pb[c.npr] = q;
+          c.ep[c.npr] = lr_edge(g, o[p], o[q]);
+          ++c.npr;
+        }
+      LrGemmArgs& h = B.h[sb];
+      h.A = g.dims[k];
+      h.Bn = 1;
+      h.I = g.dims[i];
+      h.Nn = R * (R + 1) / 2;
+      h.pairR = R;
+      h.ldb = g.dims[i];
+      LrSolveArgs& v = B.s[sb];
+      v.Ik = g.dims[k];
+      v.Ii = g.dims[i];
+      v.R = R;
+      v.nr = nr;
+      v.rho = g.rho;
+      v.ustr_j = ustr[k];
+      v.ustr_i = ustr[i];
+      for (int p = 0; p < nr; ++p) {
+        v.ustr[p] = ustr[o[p]];
+        v.urank[p] = g.R[k][o[p]];
+        v.goff_o[p] = g.goff[k][o[p]];
+      }
+      v.goff_ki = g.goff[k][i];
+      v.goff_ik = g.goff[i][k];
+      v.dtype = g.dtype;
+      v.w = lr_edge(g, k, i);
+      P->nc = std::max(P->nc, (long long)g.dims[k] * g.dims[i]);
+      P->nh = std::max(P->nh, (long long)g.dims[k] * h.Nn);
+      ++sb;
+    }
+  }
+  LrXArgs& x = P->x;
+  std::memset(&x, 0, sizeof(x));
+  x.N = N;
+  for (int m = 0; m < N; ++m) x.dims[m] = g.dims[m];
+  x.nX = g.nX;
+  x.ne = g.ne;
+  for (int e = 0; e < g.ne; ++e) {
+    x.ea[e] = g.ea[e];
+    x.eb[e] = g.eb[e];
+    x.woff[e] = g.woff[e];
+  }
+  x.rx = g.rho_x;
+  x.inv1 = 1.0 / (1.0 + g.rho_x);
+  P->xblk = (int)std::min<long long>(1024, std::max<long long>(1, (g.nX + NT - 1) / NT));
+  return true;
+}
+
+// Device pointers of every launch; buf0/buf1 the mode-product buffers.
+void lr_bind(LrPlan* P, const Geo& g, const void* X, const uint32_t* bits, double* G, double* W64, void* Wc,
+             double* buf0, double* buf1, double* cbuf, double* hbuf, double* normpart, double* dgpart,
+             const int* stop) {
+  long long dgo = 0;
+  for (int k = 0; k < g.N; ++k) {
+    LrBlock& B = P->b[k];
+    B.y.X = X;
+    B.y.W64 = W64;
+    B.y.Y = buf0;
+    B.y.stop = stop;
+    const double* in = buf0;
+    for (int t = 0; t < B.nst; ++t) {
+      LrGemmArgs& a = B.st[t];
+      double* out = B.st_out1[t] ? buf1 : buf0;
+      a.in = in;
+      a.out = out;
+      int m = -1;                      // the mode of stage t: modes != k from the last down
+      for (int q = g.N - 1, n = 0; q >= 0; --q) {
+        if (q == k) continue;
+        if (n++ == t) {
+          m = q;
+          break;
+        }
+      }
+      a.Bm = G + g.goff[m][k];
+      a.stop = stop;
+      in = out;
+    }
+    for (int t = 0; t < g.N - 1; ++t) {
+      B.c[t].W64 = W64;
+      B.c[t].c = cbuf;
+      B.c[t].stop = stop;
+      int i = -1;
+      for (int q = 0, n = 0; q < g.N; ++q) {
+        if (q == k) continue;
+        if (n++ == t) {
+          i = q;
+          break;
+        }
+      }
+      B.h[t].in = cbuf;
+      B.h[t].Bm = G + g.goff[i][k];
+      B.h[t].out = hbuf;
+      B.h[t].stop = stop;
+      LrSolveArgs& v = B.s[t];
+      v.U = in;
+      v.H = hbuf;
+      v.G = G;
+      v.W64 = W64;
+      v.Wc = Wc;
+      v.dgpart = dgpart + dgo + (long long)t * g.dims[k];
+      v.stop = stop;
+    }
+    dgo += (long long)(g.N - 1) * g.dims[k];
+  }
+  P->x.X = (void*)X;
+  P->x.bits = bits;
+  P->x.W64 = W64;
+  P->x.normpart = normpart;
+  P->x.stop = stop;
+}
+
 struct ifctn_job {
   Geo g;
   PlanOpts opts;              // tuning options the job was planned with
@@ -817,6 +1047,8 @@ struct ifctn_job {
   bool merge[MAXN] = {};       // Gram weights inside the contraction launch
   PhaseArgs pplan[MAXN][MAXN - 1];
   int nnorm = 0, ndg = 0;
+  bool lr = false;             // large-rank route for every block (an edge rank above MAXR)
+  LrPlan lp;
   bool pending = false;
   int sweeps_done = 0;
   // device-side stop test (Algorithm 1) after every X step: flag[1] = stop,
@@ -832,8 +1064,41 @@ namespace {
 
 struct Sizes {
   size_t x, xb, bits, G, W64, Wc, Q, Upart, Ugrp, ucnt, Ufin, Hpart, hcnt, normpart, dgpart, stats, flag, qitems;
-  size_t gamma, gmpart, gmcnt, grec, gtab, total;
+  size_t gamma, gmpart, gmcnt, grec, gtab;
+  size_t lr0, lr1, lrc, lrh;   // large-rank route: Y / mode-product buffers, c weights, packed H rows
+  size_t total;
 };
+
+size_t sizes_total(const Sizes& s) {
+  return s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ugrp + s.ucnt + s.Ufin + s.Hpart + s.hcnt +
+         s.normpart + s.dgpart + s.stats + s.flag + s.qitems + s.gamma + s.gmpart + s.gmcnt + s.grec + s.gtab +
+         s.lr0 + s.lr1 + s.lrc + s.lrh;
+}
+
+// arena of a large-rank job: X, mask bits, factors, edges, statistics and the
+// route's own buffers (none of the fused route's)
+Sizes lr_sizes(const Geo& g, const LrPlan& P) {
+  Sizes s{};
+  s.x = al256(g.nX * g.esz);
+  s.bits = al256(((g.nX + 63) / 64) * 8);
+  s.G = al256(g.nG * 8);
+  s.W64 = al256(g.nW * 8);
+  s.Wc = al256(g.nW * g.esz);
+  long long ndg = 0;
+  for (int k = 0; k < g.N; ++k) ndg += (long long)(g.N - 1) * g.dims[k];
+  s.normpart = al256((size_t)P.xblk * 3 * 8);
+  s.dgpart = al256(ndg * 8);
+  s.stats = al256(8 * 8);
+  s.flag = al256(16);
+  s.qitems = al256(sizeof(QItem) * MAXN * (MAXN - 1));
+  s.grec = al256(sizeof(GammaPlan) * MAXN) + al256(sizeof(GSolve) * MAXN);
+  s.lr0 = al256(P.n0 * 8);
+  s.lr1 = al256(P.n1 * 8);
+  s.lrc = al256(P.nc * 8);
+  s.lrh = al256(P.nh * 8);
+  s.total = sizes_total(s);
+  return s;
+}
 
 bool use_phased(const Geo& g, const QArgs& Q, int k, const PlanOpts& o) {
   long long m = 0;
@@ -859,11 +1124,10 @@ int hp_width(int Ik) {
   return w;
 }
 
-size_t al256(size_t x) { return (x + 255) & ~size_t(255); }
 
 Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o, GammaPlan* gpl = nullptr,
                 GSolve* gsl = nullptr, bool* groute = nullptr) {
-  Sizes s;
+  Sizes s{};
   s.x = al256(g.nX * g.esz);
   s.xb = g.bf16 ? al256(g.nX * 2) : 0;
   s.bits = al256(((g.nX + 63) / 64) * 8);
@@ -942,9 +1206,7 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o, Ga
   s.gmcnt = al256(gmcnt * 4);
   s.grec = al256(sizeof(GammaPlan) * MAXN) + al256(sizeof(GSolve) * MAXN);
   s.gtab = al256(gtab * 4);
-  s.total = s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ugrp + s.ucnt + s.Ufin + s.Hpart + s.hcnt +
-            s.normpart + s.dgpart +
-            s.stats + s.flag + s.qitems + s.gamma + s.gmpart + s.gmcnt + s.grec + s.gtab;
+  s.total = sizes_total(s);
   return s;
 }
 
@@ -1135,7 +1397,61 @@ hipError_t do_solve(ifctn_job* J, const void* c) {
   return e;
 }
 
+hipError_t do_lr_x(ifctn_job* J, const void*) {
+  return launch_lr_x(J->g.dtype, J->lp.x, J->lp.xblk, J->stream);
+}
+
+hipError_t do_lr_contract(ifctn_job* J, const void* c) {
+  const LrBlock& B = J->lp.b[*(const int*)c];
+  hipError_t e = launch_lr_y(J->g.dtype, B.y, J->stream);
+  for (int t = 0; t < B.nst && e == hipSuccess; ++t) e = launch_lr_gemm(B.st[t], J->stream);
+  return e;
+}
+
+struct LrSub {
+  int k, t;
+};
+
+hipError_t do_lr_gram(ifctn_job* J, const void* c) {
+  const LrSub* q = (const LrSub*)c;
+  const LrBlock& B = J->lp.b[q->k];
+  hipError_t e = launch_lr_c(B.c[q->t], J->stream);
+  if (e == hipSuccess) e = launch_lr_gemm(B.h[q->t], J->stream);
+  return e;
+}
+
+hipError_t do_lr_solve(ifctn_job* J, const void* c) {
+  const LrSub* q = (const LrSub*)c;
+  return launch_lr_solve(J->lp.b[q->k].s[q->t], J->stream);
+}
+
+// one sweep of the large-rank route: the pending X step (and stop test),
+// then for every k: Y and the mode products into U_k, and per sub-block the
+// weights, H rows and the column solves
+hipError_t lr_sweep(ifctn_job* J) {
+  hipError_t e;
+  if (J->pending) {
+    e = timed(J, KC_UPDATE, do_lr_x, nullptr);
+    if (e == hipSuccess && J->dev_stop) e = launch_stop_test(J->normpart, J->nnorm, J->stop_eps, J->flag + 1, J->stream);
+    if (e != hipSuccess) return e;
+  }
+  for (int k = 0; k < J->g.N; ++k) {
+    e = timed(J, KC_CONTRACT, do_lr_contract, &k);
+    if (e != hipSuccess) return e;
+    for (int t = 0; t < J->g.N - 1; ++t) {
+      const LrSub q{k, t};
+      e = timed(J, KC_GRAM, do_lr_gram, &q);
+      if (e == hipSuccess) e = timed(J, KC_SOLVE, do_lr_solve, &q);
+      if (e != hipSuccess) return e;
+    }
+  }
+  J->pending = true;
+  J->sweeps_done++;
+  return hipSuccess;
+}
+
 hipError_t run_sweep(ifctn_job* J) {
+  if (J->lr) return lr_sweep(J);
   const int N = J->g.N;
   hipError_t e;
   for (int k = 0; k < N; ++k) {
@@ -1165,7 +1481,7 @@ hipError_t run_sweep(ifctn_job* J) {
 hipError_t flush_update(ifctn_job* J) {
   if (!J->pending) return hipSuccess;
   ContractCall cc{0, true, false};
-  hipError_t e = timed(J, KC_UPDATE, do_contract, &cc);
+  hipError_t e = J->lr ? timed(J, KC_UPDATE, do_lr_x, nullptr) : timed(J, KC_UPDATE, do_contract, &cc);
   J->pending = false;
   if (e == hipSuccess && J->dev_stop) e = launch_stop_test(J->normpart, J->nnorm, J->stop_eps, J->flag + 1, J->stream);
   return e;
@@ -1267,9 +1583,20 @@ size_t ifctn_workspace_bytes(const ifctn_params* params) { return job_bytes(para
 
 namespace ifctn {
 
+ifctn_status lr_check(const Geo& g, LrPlan* P) {
+  if (g.bf16) return fail(IFCTN_E_UNSUPPORTED, "BF16_REFINE supports edge ranks up to %d", MAXR);
+  if (!plan_lr(g, P)) return fail(IFCTN_E_UNSUPPORTED, "a mode product of the large-rank route exceeds 2^31 entries");
+  return IFCTN_OK;
+}
+
 size_t job_bytes(const ifctn_params* params, const PlanOpts& o) {
   Geo g;
   if (make_geo(params, &g) != IFCTN_OK) return 0;
+  if (large_ranks(g)) {
+    LrPlan P;
+    if (lr_check(g, &P) != IFCTN_OK) return 0;
+    return lr_sizes(g, P).total;
+  }
   ContractPlan cp[MAXN];
   const Sizes s = job_sizes(g, cp, nullptr, o);
   const char* why = "";
@@ -1312,8 +1639,16 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   J->g = g;
   J->stream = (hipStream_t)stream;
   J->opts = opts;
-  const Sizes s = job_sizes(g, J->cplan, J->qplan, opts, J->gplan, J->gsol, J->groute);
-  for (int k = 0; k < g.N; ++k) {
+  J->lr = large_ranks(g);
+  if (J->lr) {
+    st = lr_check(g, &J->lp);
+    if (st != IFCTN_OK) {
+      delete J;
+      return st;
+    }
+  }
+  const Sizes s = J->lr ? lr_sizes(g, J->lp) : job_sizes(g, J->cplan, J->qplan, opts, J->gplan, J->gsol, J->groute);
+  for (int k = 0; k < g.N && !J->lr; ++k) {
     const char* why = "";
     if (!plan_ok(g, J->cplan[k], &why)) {
       delete J;
@@ -1362,9 +1697,21 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   J->dgp = (GammaPlan*)p;        p += al256(sizeof(GammaPlan) * MAXN);
   J->dgs = (GSolve*)p;           p += al256(sizeof(GSolve) * MAXN);
   int* dtab = (int*)p;           p += s.gtab;
+  double* lrb0 = (double*)p;     p += s.lr0;
+  double* lrb1 = (double*)p;     p += s.lr1;
+  double* lrc = (double*)p;      p += s.lrc;
+  double* lrh = (double*)p;      p += s.lrh;
   std::vector<int>& htab = J->htab;
   J->bf16_phase = g.bf16;
-  for (int k = 0; k < g.N; ++k) {
+  if (J->lr) {
+    lr_bind(&J->lp, g, J->X, J->bits, J->G, J->W64, J->Wc, lrb0, lrb1, lrc, lrh, J->normpart, J->dgpart,
+            J->flag + 1);
+    J->nnorm = J->lp.xblk;
+    long long ndg = 0;
+    for (int k = 0; k < g.N; ++k) ndg += (long long)(g.N - 1) * g.dims[k];
+    J->ndg = (int)ndg;
+  }
+  for (int k = 0; k < g.N && !J->lr; ++k) {
     ContractArgs& a = J->cplan[k].a;
     a.X = g.bf16 ? (void*)J->Xb : J->X;
     a.maskbits = J->bits;
@@ -1381,9 +1728,11 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
     a.stop = J->flag + 1;
     J->qplan[k].stop = J->flag + 1;
   }
-  J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
-  build_solve_plans(J);
-  for (int k = 0; k < g.N; ++k) {
+  if (!J->lr) {
+    J->nnorm = J->cplan[0].a.JT * J->cplan[0].a.S * J->cplan[0].a.FS;
+    build_solve_plans(J);
+  }
+  for (int k = 0; k < g.N && !J->lr; ++k) {
     if (!J->groute[k]) continue;
     GammaPlan& gp = J->gplan[k];
     gp.W64 = J->W64;
@@ -1427,7 +1776,7 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
     J->splan[k].stop = J->flag + 1;
     for (int t = 0; t < g.N - 1; ++t) J->pplan[k][t].stop = J->flag + 1;
   }
-  for (int k = 0; k < g.N; ++k) {
+  for (int k = 0; k < g.N && !J->lr; ++k) {
     const bool too_big = !J->groute[k] && (J->phased[k] ? (size_t)J->splan[k].Rprod * 8 > kMaxLds
                                                         : solve_smem_bytes(J->splan[k]) > kMaxLds);
     if (too_big) {
@@ -1457,7 +1806,7 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   if (!htab.empty())
     INIT_TRY(hipMemcpyAsync(dtab, htab.data(), htab.size() * sizeof(int), hipMemcpyHostToDevice, J->stream));
   INIT_TRY(hipMemcpyAsync(J->G, G0_host, g.nG * 8, hipMemcpyHostToDevice, J->stream));
-  for (int k = 0; k < g.N; ++k)
+  for (int k = 0; k < g.N && !J->lr; ++k)
     INIT_TRY(hipMemcpyAsync((void*)J->qplan[k].dit, J->qplan[k].it, sizeof(QItem) * (MAXN - 1),
                             hipMemcpyHostToDevice, J->stream));
   INIT_TRY(launch_init_x(g.dtype, O_dev, mask_dev, J->X, J->bits, J->flag, g.nX, J->stream));
@@ -1711,6 +2060,17 @@ ifctn_status ifctn_plan_blocks(const ifctn_params* params, ifctn_block_plan* out
   Geo g;
   ifctn_status st = make_geo(params, &g);
   if (st != IFCTN_OK) return st;
+  if (large_ranks(g)) {
+    LrPlan P;
+    st = lr_check(g, &P);
+    if (st != IFCTN_OK) return st;
+    for (int k = 0; k < g.N; ++k) {
+      out[k].route = 3;
+      out[k].reserved = 0;
+      out[k].gamma_fma = 0.0;
+    }
+    return IFCTN_OK;
+  }
   const PlanOpts o = current_opts();
   ContractPlan cp[MAXN];
   QArgs qp[MAXN];

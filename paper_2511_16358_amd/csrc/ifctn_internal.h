@@ -315,6 +315,109 @@ struct ReconArgs {
   void* out;
 };
 
+// --------------------------------------------------------------------------
+// Large-rank route: the factor blocks of a job with any edge rank above MAXR
+// (up to LR_MAXR).  Every quantity of eq. (updateG) is formed explicitly in
+// float64 with rank-generic kernels:
+//   Y   = X o D_{-k}                 (D_{-k}: the edge factors not touching k)
+//   U_k = Y x_{a != k} G_{a,k}       (one mode product per mode a != k)
+//   c_j(y) = sum over the other modes of the squared edge factors, so that
+//   H_j = G_{i,k} diag(c_j) G_{i,k}^T + rho I,  b_j = U_k(j) . (g_{k,a})_{a != k,i} + rho g_j
+// and one Cholesky factorisation per column.
+// --------------------------------------------------------------------------
+constexpr int LR_MAXR = 36;                              // IFCTN_MAX_RANK
+constexpr int LR_MAXP = LR_MAXR * (LR_MAXR + 1) / 2;     // distinct entries of a 36 x 36 Gram matrix
+
+struct LrEdge {          // W(x, y) = W64[off + x * s1 + y * s2], either orientation of a stored W_ab
+  long long off, s1, s2;
+};
+
+// Y = X o D_{-k}: X times every edge factor W_ab(i_a, i_b) with a, b != k
+struct LrYArgs {
+  int N;
+  int dims[MAXN];
+  long long nX;
+  int ne;
+  int ea[10], eb[10];
+  long long woff[10];
+  const void* X;
+  const double* W64;
+  double* Y;
+  const int* stop;
+};
+
+// out[a][n][b] = sum_x in[a][x][b] * B(n, x) for a < A, n < Nn, b < Bn, x < I,
+// with B(n, x) = Bm[n * ldb + x], or for pairR > 0 the packed Gram pair
+// n = (r, r'), r <= r' < pairR: B(n, x) = Bm[r * ldb + x] * Bm[r' * ldb + x]
+struct LrGemmArgs {
+  long long A, Bn;
+  int I, Nn, pairR;
+  long long ldb;
+  const double* in;
+  const double* Bm;
+  double* out;
+  const int* stop;
+};
+
+// c(j, y) for j < Ik (mode k), y < Ii (mode i): over the nr = N - 2 other
+// modes a, the sum of prod_a W_ka(j, x_a)^2 W_ia(y, x_a)^2 times
+// prod_{pairs a < b} W_ab(x_a, x_b)^2
+struct LrCArgs {
+  int Ik, Ii, nr;
+  int rdim[MAXN];
+  LrEdge ek[MAXN], ei[MAXN];
+  int npr;
+  int pa[10], pb[10];       // positions in rdim
+  LrEdge ep[10];
+  const double* W64;
+  double* c;
+  const int* stop;
+};
+
+// one column j of G_{k,i} per workgroup: b_j from U_k, H_j from the packed
+// Gram rows, Cholesky, the new column, its ||dg||^2 and row j of W_{k,i}
+struct LrSolveArgs {
+  int Ik, Ii, R, nr;
+  double rho;
+  const double* U;
+  long long ustr_j, ustr_i;
+  long long ustr[MAXN];     // the other modes a != k, i
+  int urank[MAXN];
+  long long goff_o[MAXN];   // G_{k,a} of those modes
+  long long goff_ki, goff_ik;
+  const double* H;          // [Ik][R (R + 1) / 2]
+  double* G;
+  double* W64;
+  void* Wc;
+  int dtype;
+  LrEdge w;                 // W_{k,i}(j, y)
+  double* dgpart;           // [Ik] of this sub-block
+  const int* stop;
+};
+
+// eq. (updateX) with the reconstruction of eq. (iFCTN) from W64 and the
+// partial norms {||dX||^2, ||X||^2, ||X_new - Xhat||^2} of each workgroup
+struct LrXArgs {
+  int N;
+  int dims[MAXN];
+  long long nX;
+  int ne;
+  int ea[10], eb[10];
+  long long woff[10];
+  void* X;
+  const uint32_t* bits;
+  const double* W64;
+  double rx, inv1;
+  double* normpart;
+  const int* stop;
+};
+
+hipError_t launch_lr_y(int dtype, const LrYArgs& a, hipStream_t s);
+hipError_t launch_lr_gemm(const LrGemmArgs& a, hipStream_t s);
+hipError_t launch_lr_c(const LrCArgs& a, hipStream_t s);
+hipError_t launch_lr_solve(const LrSolveArgs& a, hipStream_t s);
+hipError_t launch_lr_x(int dtype, const LrXArgs& a, int nblk, hipStream_t s);
+
 // kernel classes for timing
 enum KernelClass { KC_CONTRACT = 0, KC_SOLVE = 1, KC_UPDATE = 2, KC_GRAM = 3, KC_COUNT = 4 };
 

@@ -23,7 +23,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libifctn.so")
 
 IFCTN_MAX_ORDER = 5
-IFCTN_MAX_RANK = 8
+IFCTN_MAX_RANK = 36
 IFCTN_OK, IFCTN_E_INVAL, IFCTN_E_NOMEM, IFCTN_E_HIP, IFCTN_E_STATE, IFCTN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 IFCTN_FP32, IFCTN_BF16_REFINE, IFCTN_FP64 = 0, 1, 2
 KC_CONTRACT, KC_SOLVE, KC_UPDATE, KC_GRAM = 0, 1, 2, 3
@@ -185,7 +185,7 @@ def num_factor_entries(dims, ranks) -> int:
     return int(lib().ifctn_num_factor_entries(ctypes.byref(make_params(dims, ranks))))
 
 
-ROUTE_PERCOLUMN, ROUTE_PHASED, ROUTE_GAMMA = 0, 1, 2
+ROUTE_PERCOLUMN, ROUTE_PHASED, ROUTE_GAMMA, ROUTE_LARGE = 0, 1, 2, 3
 
 
 def plan_blocks(dims, ranks, precision=IFCTN_FP32):

@@ -396,11 +396,10 @@ def rank_grid_uniform(N: int, values=(2, 3, 4, 5, 6, 7, 8)):
     return [uniform_ranks(N, v) for v in values]
 
 
-def rank_grid_msi(r12=(2, 3, 6), r13=(3, 6)):
+def rank_grid_msi(r12=(3, 6, 9, 15, 30, 36), r13=(3, 6, 9)):
     """The image rank grid of Sec. 5 for order-3 tensors: R_{1,2} over one set
-    and R_{1,3} = R_{2,3} over another (0-based modes: R[0][1], R[0][2] = R[1][2]).
-    The paper's sets reach 36; this library supports ranks up to 8, so the
-    default sets are the paper's values up to 8."""
+    and R_{1,3} = R_{2,3} over another (0-based modes: R[0][1], R[0][2] = R[1][2]),
+    18 rank matrices by default."""
     out = []
     for a in r12:
         for b in r13:

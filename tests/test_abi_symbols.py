@@ -87,3 +87,31 @@ def test_struct_layouts_match_header(tmp_path):
         assert int(got[cname]) == ctypes.sizeof(cls), cname
         for f in fl:
             assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
+
+
+def _grid_ranks(r01, r02):
+    r = W.uniform_ranks(3, r02)
+    r[0][1] = r[1][0] = r01
+    return r
+
+
+@pytest.mark.parametrize("r01,r02", [(36, 9), (9, 3), (30, 6), (8, 9)])
+def test_large_ranks_take_the_large_rank_route(r01, r02):
+    """Any edge rank above 8 sends every block of the job down the
+    large-rank route (route 3); ranks up to 8 never do."""
+    dims = (256, 256, 31)
+    plan = ifctn.plan_blocks(dims, _grid_ranks(r01, r02))
+    assert [r for r, _ in plan] == [ifctn.ROUTE_LARGE] * 3
+    for prec in (ifctn.IFCTN_FP32, ifctn.IFCTN_FP64):
+        assert 0 < ifctn.workspace_bytes(dims, _grid_ranks(r01, r02), prec) < 256 << 20
+    assert all(r != ifctn.ROUTE_LARGE for r, _ in ifctn.plan_blocks(dims, _grid_ranks(8, 8)))
+
+
+def test_large_rank_limits():
+    """Ranks above 36 are refused; BF16_REFINE stays with ranks up to 8."""
+    assert ifctn.workspace_bytes((20, 24, 5), _grid_ranks(37, 3)) == 0
+    assert ifctn.workspace_bytes((20, 24, 5), _grid_ranks(36, 3)) > 0
+    assert ifctn.workspace_bytes((20, 24, 5), _grid_ranks(9, 3), ifctn.IFCTN_BF16_REFINE) == 0
+    assert ifctn.workspace_bytes((20, 24, 5), _grid_ranks(8, 3), ifctn.IFCTN_BF16_REFINE) > 0
+    with pytest.raises(ifctn.IfctnError):
+        ifctn.plan_blocks((20, 24, 5), _grid_ranks(9, 3), ifctn.IFCTN_BF16_REFINE)
