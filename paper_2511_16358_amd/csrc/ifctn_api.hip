@@ -905,7 +905,6 @@ bool plan_lr(const Geo& g, LrPlan* P) {
       h.ldb = g.dims[i];
       LrSolveArgs& v = B.s[sb];
       v.Ik = g.dims[k];
-      v.Ii = g.dims[i];
       v.R = R;
       v.nr = nr;
       v.rho = g.rho;
@@ -917,9 +916,6 @@ bool plan_lr(const Geo& g, LrPlan* P) {
         v.goff_o[p] = g.goff[k][o[p]];
       }
       v.goff_ki = g.goff[k][i];
-      v.goff_ik = g.goff[i][k];
-      v.dtype = g.dtype;
-      v.w = lr_edge(g, k, i);
       P->nc = std::max(P->nc, (long long)g.dims[k] * g.dims[i]);
       P->nh = std::max(P->nh, (long long)g.dims[k] * h.Nn);
       ++sb;
@@ -991,8 +987,6 @@ void lr_bind(LrPlan* P, const Geo& g, const void* X, const uint32_t* bits, doubl
       v.U = in;
       v.H = hbuf;
       v.G = G;
-      v.W64 = W64;
-      v.Wc = Wc;
       v.dgpart = dgpart + dgo + (long long)t * g.dims[k];
       v.stop = stop;
     }
@@ -1420,9 +1414,23 @@ hipError_t do_lr_gram(ifctn_job* J, const void* c) {
   return e;
 }
 
+// the column solves, then W_{k,i} from the new G_{k,i}
 hipError_t do_lr_solve(ifctn_job* J, const void* c) {
   const LrSub* q = (const LrSub*)c;
-  return launch_lr_solve(J->lp.b[q->k].s[q->t], J->stream);
+  hipError_t e = launch_lr_solve(J->lp.b[q->k].s[q->t], J->stream);
+  if (e != hipSuccess) return e;
+  const Geo& g = J->g;
+  int i = -1;
+  for (int m = 0, n = 0; m < g.N; ++m) {
+    if (m == q->k) continue;
+    if (n++ == q->t) {
+      i = m;
+      break;
+    }
+  }
+  const int a = std::min(q->k, i), b = std::max(q->k, i), x = g.eid[a][b];
+  return launch_edge(g.dtype, J->G + g.goff[a][b], J->G + g.goff[b][a], g.R[a][b], g.dims[a], g.dims[b],
+                     J->W64 + g.woff[x], (unsigned char*)J->Wc + g.woff[x] * g.esz, J->stream);
 }
 
 // one sweep of the large-rank route: the pending X step (and stop test),

@@ -1149,20 +1149,6 @@ __global__ __launch_bounds__(NT) void k_contract_cols(ContractArgs a) {
   if (a.ugrp) group_partials(a, jt, spf, j0, jcnt);
 }
 
-// Per-launch timing (events set by set_kernel_events; see ifctn_kernels.hip)
-extern thread_local hipEvent_t tl_ev_start, tl_ev_stop;
-extern thread_local bool tl_ev_used;
-
-#define IFCTN_GO(kern, grid, blk, smem, s, ...)                                                   \
-  do {                                                                                            \
-    if (tl_ev_start) {                                                                            \
-      hipExtLaunchKernelGGL(kern, grid, blk, smem, s, tl_ev_used ? nullptr : tl_ev_start,          \
-                            tl_ev_stop, 0u, __VA_ARGS__);                                          \
-      tl_ev_used = true;                                                                          \
-    } else {                                                                                      \
-      hipLaunchKernelGGL(kern, grid, blk, smem, s, __VA_ARGS__);                                  \
-    }                                                                                             \
-  } while (0)
 template <typename TX, typename TC>
 static hipError_t contract_dispatch(bool upd, bool con, int spt, const ContractArgs& a, size_t smem,
                                     hipStream_t s) {

@@ -2,6 +2,7 @@
 // of the iFCTN-TC library.  Not part of the public ABI (include/ifctn.h).
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
@@ -375,22 +376,18 @@ struct LrCArgs {
 };
 
 // one column j of G_{k,i} per workgroup: b_j from U_k, H_j from the packed
-// Gram rows, Cholesky, the new column, its ||dg||^2 and row j of W_{k,i}
+// Gram rows, Cholesky, the new column and its ||dg||^2
 struct LrSolveArgs {
-  int Ik, Ii, R, nr;
+  int Ik, R, nr;
   double rho;
   const double* U;
   long long ustr_j, ustr_i;
   long long ustr[MAXN];     // the other modes a != k, i
   int urank[MAXN];
   long long goff_o[MAXN];   // G_{k,a} of those modes
-  long long goff_ki, goff_ik;
+  long long goff_ki;
   const double* H;          // [Ik][R (R + 1) / 2]
   double* G;
-  double* W64;
-  void* Wc;
-  int dtype;
-  LrEdge w;                 // W_{k,i}(j, y)
   double* dgpart;           // [Ik] of this sub-block
   const int* stop;
 };
@@ -411,6 +408,24 @@ struct LrXArgs {
   double* normpart;
   const int* stop;
 };
+
+// Per-launch timing (events set by set_kernel_events; see ifctn_kernels.hip):
+// with events set, a launcher goes through hipExtLaunchKernel, which stamps
+// the start event with its first kernel's start and the stop event with the
+// last kernel's end.
+extern thread_local hipEvent_t tl_ev_start, tl_ev_stop;
+extern thread_local bool tl_ev_used;
+
+#define IFCTN_GO(kern, grid, blk, smem, s, ...)                                                   \
+  do {                                                                                            \
+    if (tl_ev_start) {                                                                            \
+      hipExtLaunchKernelGGL(kern, grid, blk, smem, s, tl_ev_used ? nullptr : tl_ev_start,          \
+                            tl_ev_stop, 0u, __VA_ARGS__);                                          \
+      tl_ev_used = true;                                                                          \
+    } else {                                                                                      \
+      hipLaunchKernelGGL(kern, grid, blk, smem, s, __VA_ARGS__);                                  \
+    }                                                                                             \
+  } while (0)
 
 hipError_t launch_lr_y(int dtype, const LrYArgs& a, hipStream_t s);
 hipError_t launch_lr_gemm(const LrGemmArgs& a, hipStream_t s);

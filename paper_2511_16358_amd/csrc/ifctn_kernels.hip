@@ -1041,9 +1041,9 @@ hipError_t launch_edge(int dtype, const double* Gab, const double* Gba, int R, i
                        void* Wc, hipStream_t s) {
   const long long n = (long long)Ia * Ib;
   if (dtype == 0)
-    hipLaunchKernelGGL(k_edge<float>, dim3(nblk(n)), dim3(NT), 0, s, Gab, Gba, R, Ia, Ib, W64, (float*)Wc);
+    IFCTN_GO(k_edge<float>, dim3(nblk(n)), dim3(NT), 0, s, Gab, Gba, R, Ia, Ib, W64, (float*)Wc);
   else
-    hipLaunchKernelGGL(k_edge<double>, dim3(nblk(n)), dim3(NT), 0, s, Gab, Gba, R, Ia, Ib, W64, (double*)Wc);
+    IFCTN_GO(k_edge<double>, dim3(nblk(n)), dim3(NT), 0, s, Gab, Gba, R, Ia, Ib, W64, (double*)Wc);
   return hipGetLastError();
 }
 // Per-launch timing: when events are set, the hot-path launchers go through
