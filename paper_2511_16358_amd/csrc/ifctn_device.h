@@ -15,6 +15,15 @@
 
 namespace ifctn {
 
+// An empty register pin: the value counts as used where the pin stands, so
+// the compiler cannot sink the load that produced it into a later
+// conditional use (which would make each load of a batch wait for the
+// previous one).  The loads of a batch are all issued before the first pin.
+template <typename T>
+__device__ __forceinline__ T pin(T v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
 
 // --------------------------------------------------------------------------
 // small helpers
@@ -58,17 +67,24 @@ __device__ __forceinline__ void gram_rows(const double* __restrict__ W64, const 
 #pragma unroll
       for (int u = 0; u < XU; ++u) {
         const int x = min(x0 + u, hi - 1);
+        // every load unconditional: unused edge records are zero (offset
+        // and strides), so they read W64[0]; their factor is replaced by 1
 #pragma unroll
-        for (int c = 0; c < MAXC; ++c) wv[u][c] = c < nd ? W64[eaddr(it.edi[c], im[c], x)] : 1.0;
+        for (int c = 0; c < MAXC; ++c) wv[u][c] = W64[eaddr(it.edi[c], im[c], x)];
 #pragma unroll
         for (int r = R0; r < R; ++r) g[u][r] = Gik[(long long)r * Ii + x];
+      }
+#pragma unroll
+      for (int u = 0; u < XU; ++u) {
+#pragma unroll
+        for (int c = 0; c < MAXC; ++c) wv[u][c] = pin(wv[u][c]);
       }
 #pragma unroll
       for (int u = 0; u < XU; ++u) {
         const double live = (x0 + u < hi) ? 1.0 : 0.0;
         double w = sdd * live;
 #pragma unroll
-        for (int c = 0; c < MAXC; ++c) w *= wv[u][c] * wv[u][c];
+        for (int c = 0; c < MAXC; ++c) w *= c < nd ? wv[u][c] * wv[u][c] : 1.0;
         int p = 0;
 #pragma unroll
         for (int r = R0; r < R1; ++r) {
@@ -111,16 +127,19 @@ __device__ __forceinline__ void gram_work(const double* __restrict__ W64, const 
         t /= it.ddim[c];
       }
     }
+    double wd[3];
 #pragma unroll
-    for (int q = 0; q < 3; ++q) {
-      if (q < ndd) {
-        const int xa = it.dd_a[q], xb = it.dd_b[q];
-        const int ia = xa == 0 ? im[0] : (xa == 1 ? im[1] : im[2]);
-        const int ib = xb == 0 ? im[0] : (xb == 1 ? im[1] : im[2]);
-        const double w = W64[eaddr(it.edd[q], ia, ib)];
-        sdd *= w * w;
-      }
+    for (int q = 0; q < 3; ++q) {   // unused records are zero: they read W64[0]
+      const int xa = it.dd_a[q], xb = it.dd_b[q];
+      const int ia = xa == 0 ? im[0] : (xa == 1 ? im[1] : im[2]);
+      const int ib = xb == 0 ? im[0] : (xb == 1 ? im[1] : im[2]);
+      wd[q] = W64[eaddr(it.edd[q], ia, ib)];
     }
+#pragma unroll
+    for (int q = 0; q < 3; ++q) wd[q] = pin(wd[q]);
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+      if (q < ndd) sdd *= wd[q] * wd[q];
   } else {
 #pragma unroll
     for (int c = 0; c < MAXC; ++c) im[c] = 0;
@@ -197,6 +216,8 @@ __device__ __forceinline__ double ordered_sum(double s, int n, Load load, Term t
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = load(min(u0 + u, n - 1));
 #pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = pin(v[u]);
+#pragma unroll
     for (int u = 0; u < U; ++u)
       if (u0 + u < n) s += term(u0 + u, v[u]);
   }
@@ -212,6 +233,8 @@ __device__ __forceinline__ void for_batched(int n, Load load, Use use) {
     decltype(load(0)) v[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) v[u] = load(min(eb + u * NT, n - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = pin(v[u]);
 #pragma unroll
     for (int u = 0; u < U; ++u)
       if (eb + u * NT < n) use(eb + u * NT, v[u]);
@@ -736,9 +759,9 @@ __device__ __forceinline__ void load_gf(const ContractArgs& a, TC* gf, int flo, 
       fcn * MAXR,
       [&](int e) {
         const int ff = e / MAXR, r = e - ff * MAXR;
-        return r < Rf ? a.G[a.gfoff + (long long)r * If + flo + ff] : 0.0;
+        return a.G[a.gfoff + (long long)min(r, Rf - 1) * If + flo + ff];   // in bounds; padding zeroed below
       },
-      [&](int e, double v) { gf[e] = (TC)v; });
+      [&](int e, double v) { gf[e] = (e % MAXR) < Rf ? (TC)v : (TC)0; });
 }
 
 template <int SPT>
@@ -867,9 +890,9 @@ __device__ __forceinline__ void load_gl(const ContractArgs& a, double* gl) {
       cdl * MAXR,
       [&](int e) {
         const int i = e / MAXR, r = e - i * MAXR;
-        return r < Rl ? a.G[a.gloff + (long long)r * cdl + i] : 0.0;
+        return a.G[a.gloff + (long long)min(r, Rl - 1) * cdl + i];   // in bounds; padding zeroed below
       },
-      [&](int e, double v) { gl[e] = v; });
+      [&](int e, double v) { gl[e] = (e % MAXR) < Rl ? v : 0.0; });
 }
 
 __device__ __forceinline__ void block_norms(double dx2, double x2, double f2, double* red, double* out) {

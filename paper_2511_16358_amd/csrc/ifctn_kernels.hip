@@ -500,15 +500,19 @@ __global__ __launch_bounds__(NT) void k_solve_gamma(const GSolve* __restrict__ g
 #pragma unroll
           for (int t = 0; t < MAXN - 1; ++t)
             if (e >= sbeg[t]) a = sbase[t] + (e - sbeg[t]);
-          return a < 0 ? gma[e] : G[a];
+          const double* src = a < 0 ? gma + e : G + a;   // the address is selected, the load is not
+          return *src;
         },
         [&](int e, double v) { sm[e < P ? e : (int)(gik - sm) + (e - P)] = v; });
   }
   for_batched<8>(gs->tabtot, [&](int e) { return gs->tab[e]; }, [&](int e, int v) { tab[e] = v; });
-  for (int e = tid; e < n * MAXR; e += NT) {
-    const int t = e / MAXR, r = e - t * MAXR;
-    g[e] = r < gs->R[t] ? G[gs->goff_ki[t] + (long long)r * Ik + j] : 0.0;
-  }
+  for_batched<4>(
+      n * MAXR,
+      [&](int e) {
+        const int t = e / MAXR, r = e - t * MAXR;
+        return G[gs->goff_ki[t] + (long long)min(r, gs->R[t] - 1) * Ik + j];   // in bounds; padding zeroed below
+      },
+      [&](int e, double v) { g[e] = (e % MAXR) < gs->R[e / MAXR] ? v : 0.0; });
   {
     const long long stride = (long long)Ik * Rprod;
     const double* up = gs->Upart + (long long)j * Rprod;

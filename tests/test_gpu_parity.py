@@ -390,7 +390,7 @@ def test_invalid_inputs_rejected():
         ifctn.Job(p.O, p.mask, p.G0, p.dims, p.ranks, rho=0.0)
     assert e.value.status == ifctn.IFCTN_E_INVAL
     with pytest.raises(ifctn.IfctnError) as e:
-        ifctn.Job(p.O, p.mask, flat, p.dims, W.uniform_ranks(3, 9))
+        ifctn.Job(p.O, p.mask, flat, p.dims, W.uniform_ranks(3, ifctn.IFCTN_MAX_RANK + 1))
     assert e.value.status == ifctn.IFCTN_E_UNSUPPORTED
 
 
