@@ -299,6 +299,10 @@ ifctn_status ifctn_plan_blocks(const ifctn_params* params, ifctn_block_plan* out
 ifctn_status ifctn_set_option(const char* name, int64_t value);
 /*   "gamma": factor-block route -- 1 (default): the Gamma route for blocks
  *   that would otherwise take the phased form, 0: never, 2: wherever it fits.
+ *   "overlap": 1 (default): a job with Gamma-route blocks builds Gamma_k on
+ *   a second stream of its own (default priority), concurrently with the
+ *   mode-k contraction, joined by an event before the solve; 0: in line on
+ *   the job's stream.  Jobs of a server always build it in line.
  *   "ugroup": the contraction's partial slots are summed in groups of this
  *   many by the last workgroup of each group (default 0: off).
  *   "inject_admit_failures": the next `value` server admissions fail with

@@ -165,7 +165,7 @@ constexpr int kTargetBlocks = 1024;
 
 // tuning options (ifctn_set_option): < 0 = default
 std::atomic<long long> g_contract_div{-1}, g_contract_emin{-1}, g_merge_gram{-1}, g_onelaunch{-1}, g_contract_jmax{-1},
-    g_ugroup{-1}, g_gamma{-1};
+    g_ugroup{-1}, g_gamma{-1}, g_overlap{-1};
 // A factor block takes the phased form when one of its Gram weight sets is
 // large: the one-workgroup-per-column kernel would stream all of Q_{k,i}
 // through each of only I_k workgroups.
@@ -183,6 +183,7 @@ PlanOpts current_opts() {
   v = g_phased_min.load();
   o.phased_min = v >= 0 ? v : kPhasedMinDefault;
   o.onelaunch = g_onelaunch.load() > 0;                  // off by default: measured slower
+  o.overlap = g_overlap.load() != 0;
   o.merge_gram = g_merge_gram.load() != 0;
   v = g_contract_div.load();
   o.contract_div = v > 0 ? v : 1280;
@@ -1041,6 +1042,10 @@ struct ifctn_job {
   bool merge[MAXN] = {};       // Gram weights inside the contraction launch
   PhaseArgs pplan[MAXN][MAXN - 1];
   int nnorm = 0, ndg = 0;
+  // Gamma route with overlap: Gamma_k is built on `side`, forked from and
+  // joined back into `stream` by the two events
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool lr = false;             // large-rank route for every block (an edge rank above MAXR)
   LrPlan lp;
   bool pending = false;
@@ -1368,7 +1373,28 @@ hipError_t do_gram(ifctn_job* J, const void* c) { return launch_q(*(const QArgs*
 
 hipError_t do_gamma(ifctn_job* J, const void* c) {
   const int k = *(const int*)c;
-  return launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream);
+  return launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream, 0);
+}
+
+// Gamma_k on the side stream, after everything enqueued on the job's stream
+// so far (the previous block's solve): it reads only factors and edge
+// matrices that are final before block k, not X or U_k
+hipError_t do_gamma_side(ifctn_job* J, const void* c) {
+  const int k = *(const int*)c;
+  hipError_t e = hipEventRecord(J->ev_fork, J->stream);
+  if (e == hipSuccess) e = hipStreamWaitEvent(J->side, J->ev_fork, 0);
+  if (e == hipSuccess) e = launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->side, 1);
+  if (e == hipSuccess) e = hipEventRecord(J->ev_join, J->side);
+  return e;
+}
+
+// the U rows of block k on the job's stream (after the contraction), then the
+// wait for Gamma_k
+hipError_t do_urow_join(ifctn_job* J, const void* c) {
+  const int k = *(const int*)c;
+  hipError_t e = launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream, 2);
+  if (e == hipSuccess) e = hipStreamWaitEvent(J->stream, J->ev_join, 0);
+  return e;
 }
 
 hipError_t do_solve(ifctn_job* J, const void* c) {
@@ -1467,6 +1493,11 @@ hipError_t run_sweep(ifctn_job* J) {
       e = timed(J, KC_GRAM, do_gram, &J->qplan[k]);
       if (e != hipSuccess) return e;
     }
+    const bool side = J->groute[k] && J->side;
+    if (side) {
+      e = timed(J, KC_GRAM, do_gamma_side, &k);
+      if (e != hipSuccess) return e;
+    }
     ContractCall cc{k, k == 0 && J->pending, true};
     e = timed(J, KC_CONTRACT, do_contract, &cc);
     if (e != hipSuccess) return e;
@@ -1475,7 +1506,7 @@ hipError_t run_sweep(ifctn_job* J) {
       if (e != hipSuccess) return e;
     }
     if (J->groute[k]) {              // Gamma_k and the U rows, then the solve
-      e = timed(J, KC_GRAM, do_gamma, &k);
+      e = side ? timed(J, KC_GRAM, do_urow_join, &k) : timed(J, KC_GRAM, do_gamma, &k);
       if (e != hipSuccess) return e;
     }
     e = timed(J, KC_SOLVE, do_solve, &J->splan[k]);
@@ -1624,6 +1655,12 @@ ifctn_status ifctn_destroy(ifctn_job* job) {
   if (!job) return IFCTN_OK;
   for (int c = 0; c < KC_COUNT; ++c)
     for (hipEvent_t e : job->ev[c]) (void)hipEventDestroy(e);
+  if (job->side) {
+    (void)hipStreamSynchronize(job->side);
+    (void)hipStreamDestroy(job->side);
+  }
+  if (job->ev_fork) (void)hipEventDestroy(job->ev_fork);
+  if (job->ev_join) (void)hipEventDestroy(job->ev_join);
   if (job->arena && job->own_arena) (void)hipFree(job->arena);
   delete job;
   return IFCTN_OK;
@@ -1798,6 +1835,15 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
     ifctn_destroy(J);
     return r;
   };
+  bool any_gamma = false;
+  for (int k = 0; k < g.N && !J->lr; ++k) any_gamma = any_gamma || J->groute[k];
+  if (any_gamma && opts.overlap) {
+    // default priority (a non-blocking stream: ordered by the events only)
+    hipError_t e = hipStreamCreateWithFlags(&J->side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&J->ev_fork, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&J->ev_join, hipEventDisableTiming);
+    if (e != hipSuccess) return bail(IFCTN_E_HIP, "side stream", e);
+  }
 #define INIT_TRY(expr)                                         \
   do {                                                         \
     hipError_t e_ = (expr);                                    \
@@ -2118,6 +2164,10 @@ ifctn_status ifctn_set_option(const char* name, int64_t value) {
   }
   if (std::strcmp(name, "gamma") == 0) {
     g_gamma.store(value < 0 ? -1 : value);
+    return IFCTN_OK;
+  }
+  if (std::strcmp(name, "overlap") == 0) {
+    g_overlap.store(value < 0 ? -1 : value);
     return IFCTN_OK;
   }
   if (std::strcmp(name, "ugroup") == 0) {

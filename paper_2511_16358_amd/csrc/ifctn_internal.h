@@ -459,7 +459,9 @@ void set_kernel_events(hipEvent_t start, hipEvent_t stop);
 bool kernel_events_used();
 hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s);
 // Gamma route: Gamma_k in a launch of its own (gm: device copy of hp), and the solve
-hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* stop, hipStream_t s);
+// part 0: both roles; 1: Gamma_k only (no dependence on X or U_k); 2: the U
+// rows only (after the contraction of block k)
+hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* stop, hipStream_t s, int part);
 hipError_t launch_solve_gamma(int dtype, const GSolve& hs, const GSolve* gs, hipStream_t s);
 size_t solve_smem_bytes(const SolveArgs& a);
 // phased factor block: U rows into Ufin, then per sub-block k_hpart + k_solve_col

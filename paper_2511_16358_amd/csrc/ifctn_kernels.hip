@@ -411,9 +411,9 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
 // (the new G_{k,i}(:, j) enters the weights of the later sub-blocks), and
 // rows j of every W_{k,m} are refreshed once, after the chain.
 // --------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_gamma(const GammaPlan* __restrict__ gp, const int* __restrict__ stop) {
+__global__ __launch_bounds__(NT) void k_gamma(const GammaPlan* __restrict__ gp, const int* __restrict__ stop, int b0) {
   if (stop && *stop) return;
-  const int b = (int)blockIdx.x, nw = gp->nw;
+  const int b = (int)blockIdx.x + b0, nw = gp->nw;
   if (b < nw)
     gamma_block<GM_VPT>(gp, b);
   else
@@ -1110,13 +1110,16 @@ static hipError_t allow_large_lds(K kern, int bytes, std::atomic<int>* limit) {
   return e;
 }
 
-hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* stop, hipStream_t s) {
+hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* stop, hipStream_t s, int part) {
   static std::atomic<int> big{64 << 10};
   {
     const hipError_t e = allow_large_lds(k_gamma, hp.smem, &big);
     if (e != hipSuccess) return e;
   }
-  IFCTN_GO(k_gamma, dim3((unsigned)(hp.nw + hp.nuw)), dim3(NT), (size_t)hp.smem, s, gm, stop);
+  const int b0 = part == 2 ? hp.nw : 0;
+  const int nb = part == 1 ? hp.nw : part == 2 ? hp.nuw : hp.nw + hp.nuw;
+  if (nb <= 0) return hipSuccess;
+  IFCTN_GO(k_gamma, dim3((unsigned)nb), dim3(NT), (size_t)hp.smem, s, gm, stop, b0);
   return hipGetLastError();
 }
 

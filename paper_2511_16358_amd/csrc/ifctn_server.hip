@@ -392,7 +392,11 @@ ifctn_status ifctn_server_submit(ifctn_server* S, const ifctn_request* req) {
     return set_error(IFCTN_E_INVAL, "O_dev, mask_dev, G0_host and X_out_dev are required");
   if (req->t_max < 0) return set_error(IFCTN_E_INVAL, "t_max < 0");
   if (!(req->eps >= 0.0)) return set_error(IFCTN_E_INVAL, "eps < 0");
-  const PlanOpts opts = current_opts();
+  PlanOpts opts = current_opts();
+  // resident jobs already overlap one another on their own streams; a second
+  // stream per job (Gamma_k beside the contraction) made the served mix about
+  // 20% slower, so served jobs build Gamma_k in line
+  opts.overlap = false;
   const size_t bytes = job_bytes(&req->params, opts);
   if (bytes == 0) return IFCTN_E_INVAL;  // message set by the params check
   if (PoolAlloc::rounded(bytes) > S->cfg.hbm_budget_bytes)

@@ -205,6 +205,32 @@ def test_gamma_route_matches_oracle(dims, ranks, precision):
     assert abs(g["dg_norm2"] - o["dg_norm2"]) <= 100 * tol * max(o["dg_norm2"], 1e-30)
 
 
+@pytest.mark.parametrize("dims,ranks", [SMALL[3], SMALL[4], SMALL[8]], ids=["5x6x7x3", "4x3x5x2x3", "8x7x9x6x10"])
+def test_gamma_overlap_is_bitwise_inline(dims, ranks):
+    """Gamma_k built on the job's second stream, concurrently with the
+    contraction, and in line on the job's stream: the same kernels on the same
+    data, so bitwise the same X, factors and statistics."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem(dims, ranks, seed=61, keep=0.5)
+    out = []
+    ifctn.set_option("gamma", 2)
+    try:
+        for ov in (1, 0):
+            ifctn.set_option("overlap", ov)
+            job = ifctn.Job(p.O, p.mask, p.G0, p.dims, p.ranks, rho=p.rho, precision=ifctn.IFCTN_FP32)
+            st = job.sweep(4)
+            out.append((job.x().cpu().numpy(), job.factors(), st))
+            job.close()
+    finally:
+        ifctn.set_option("overlap", -1)
+        ifctn.set_option("gamma", -1)
+    (xa, ga, sa), (xb, gb, sb) = out
+    assert np.array_equal(xa, xb)
+    for key in ga:
+        assert np.array_equal(ga[key], gb[key]), key
+    assert sa["objective"] == sb["objective"] and sa["dg_norm2"] == sb["dg_norm2"]
+
+
 @pytest.mark.parametrize("dims,ranks", SMALL[:5], ids=["x".join(map(str, d)) for d, _ in SMALL[:5]])
 def test_separate_gram_launch_matches_oracle(dims, ranks):
     """The Gram weights as a launch of their own (the default puts them in the
