@@ -47,6 +47,12 @@ def parse():
     ap.add_argument("--serve-round", type=int, default=10)
     ap.add_argument("--serve-sequential", type=int, default=32,
                     help="requests of the mix also run alone, one after another (0 = skip)")
+    ap.add_argument("--serve-sustained-rate", type=float, default=30.0,
+                    help="arrival rate (requests/s) of a second, shorter served run at a load the server keeps up with")
+    ap.add_argument("--serve-sustained-requests", type=int, default=128)
+    ap.add_argument("--ranks", default="",
+                    help="edge ranks R[a][b], a < b, row by row (e.g. 36,9,9), replacing the workload's; "
+                         "initial factors are drawn for them")
     ap.add_argument("--no-tuning", action="store_true", help="skip the rank-grid tuning leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-baseline-only", default=None, metavar="WORKLOAD",
@@ -263,11 +269,13 @@ def served_inputs(ifctn, torch, specs):
     return out
 
 
-def serve_mix(ifctn, torch, args):
+def serve_mix(ifctn, torch, args, n=None, rate=None, sequential=True):
     """The served mix: requests submitted at their Poisson arrival times to a
     continuous-batching server; latency = completion - submission."""
     from paper_2511_16358_amd import workloads as W
-    specs = W.served_requests(args.serve_requests, seed=0)
+    n = args.serve_requests if n is None else n
+    rate = W.SERVED["rate"] if rate is None else rate
+    specs = W.served_requests(n, seed=0, rate=rate)
     t_gen = time.perf_counter()
     inputs = served_inputs(ifctn, torch, specs)
     t_gen = time.perf_counter() - t_gen
@@ -293,7 +301,7 @@ def serve_mix(ifctn, torch, args):
     # ifctn_complete (same precision, refinement, t_max and eps): the rate
     # without the server's overlap of jobs
     seq = None
-    nseq = min(args.serve_sequential, len(specs))
+    nseq = min(args.serve_sequential, len(specs)) if sequential else 0
     if nseq > 0:
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -331,7 +339,7 @@ def serve_mix(ifctn, torch, args):
             "sequential": seq,
             "served_over_sequential": (round((sweeps / (last - first)) / seq["sweeps_per_s"], 3)
                                        if seq else None),
-            "mix": f"{len(specs)} requests, Poisson arrivals at 200/s, orders 3-5, modes 16-256 (<= 4,194,304 entries), "
+            "mix": f"{len(specs)} requests, Poisson arrivals at {rate:g}/s, orders 3-5, modes 16-256 (<= 4,194,304 entries), "
                    "R in 2..6, sampling 5/10/30%, planted iFCTN N(0,1) unit max + N(0,0.01^2), "
                    "t_max 100, eps 1e-5"}
 
@@ -418,7 +426,7 @@ def time_sweeps(ifctn, torch, p, prec, steps, warmup):
     job.sweep(steps, stats=False)
     per = {}
     for name, kc in (("contract", ifctn.KC_CONTRACT), ("solve", ifctn.KC_SOLVE),
-                     ("update", ifctn.KC_UPDATE), ("gram", ifctn.KC_GRAM)):
+                     ("update", ifctn.KC_UPDATE), ("gram", ifctn.KC_GRAM), ("urow", ifctn.KC_UROW)):
         ms, n = job.timing_query(kc)
         per[name] = {"total_ms": ms, "launches": n, "avg_us": 1e3 * ms / max(n, 1)}
     job.timing(False)
@@ -469,7 +477,7 @@ def rooflines(ifctn, p, per, steps, esz, empty_us):
         out["gram"] = {"bound": "mfma", "achieved": round(tfs, 4), "peak": FP64_MFMA_PEAK_TFS, "unit": "TFLOP/s",
                        "frac": round(tfs / FP64_MFMA_PEAK_TFS, 5), "traffic": None,
                        "algorithmic_flops_per_launch": round(flops / per["gram"]["launches"]),
-                       "kernel": "k_gamma (Gamma_k = Z_k^T Z_k, v_mfma_f64_16x16x4f64; U rows)",
+                       "kernel": "k_gamma (Gamma_k = Z_k^T Z_k on v_mfma_f64_16x16x4f64)",
                        "avg_us": round(per["gram"]["avg_us"], 2)}
     if per["solve"]["launches"]:
         # per column and sub-block: the H and b contraction chains and the
@@ -525,6 +533,18 @@ def main():
     esz = {"fp32": 4, "fp64": 8, "bf16": 2}[args.precision]
 
     p = load_workload(ifctn, W, args.workload)
+    if args.ranks:
+        up = [int(v) for v in args.ranks.split(",")]
+        N = len(p.dims)
+        if len(up) != N * (N - 1) // 2:
+            sys.exit(f"--ranks needs {N * (N - 1) // 2} values for an order-{N} workload")
+        r = np.zeros((N, N), dtype=np.int64)
+        it = iter(up)
+        for a in range(N):
+            for b in range(a + 1, N):
+                r[a][b] = r[b][a] = next(it)
+        p = W.Problem(p.name, p.dims, r, p.O, p.mask, p.X_true, W.initial_factors_for(p, r, seed=1), p.rho,
+                      p.sweeps, p.meta)
     gpu_ms, wall, per, st, job = time_sweeps(ifctn, torch, p, prec, args.steps, args.warmup)
     ms_per_step = gpu_ms / args.steps
     sweeps_per_s = args.steps / (gpu_ms / 1e3)
@@ -570,6 +590,12 @@ def main():
     served = None
     if not args.no_serve:
         served = serve_mix(ifctn, torch, args)
+        if args.serve_sustained_requests > 0:
+            sus = serve_mix(ifctn, torch, args, n=args.serve_sustained_requests, rate=args.serve_sustained_rate,
+                            sequential=False)
+            served["sustained_load"] = {k: sus[k] for k in ("requests", "failed", "p50_latency_ms", "p99_latency_ms",
+                                                            "mean_queue_ms", "aggregate_sweeps_per_s", "makespan_s",
+                                                            "arrival_window_s", "mix")}
 
     tune = None
     if not args.no_tuning:
@@ -593,10 +619,13 @@ def main():
         "dtype": {"fp32": "f32", "fp64": "f64", "bf16": "bf16"}[args.precision],
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {W.DESCRIPTIONS[args.workload]}",
-                   "dims": list(p.dims), "rank": int(p.ranks[0][1]), "rho": p.rho,
+                   "dims": list(p.dims), "rank": int(p.ranks[0][1]),
+                   "ranks_upper": [int(p.ranks[a][b]) for a in range(len(p.dims)) for b in range(a + 1, len(p.dims))],
+                   "rho": p.rho,
                    "precision": f"{args.precision} X streaming ({'float64' if args.precision == 'fp64' else 'float32'} arithmetic), "
                                 "fp64 Gram/LDL^T/factors/reductions",
-                   "routes": [["per-column", "phased", "gamma"][r] for r, _ in ifctn.plan_blocks(p.dims, p.ranks)],
+                   "routes": [["per-column", "phased", "gamma", "large-rank"][r]
+                              for r, _ in ifctn.plan_blocks(p.dims, p.ranks)],
                    "parallelism": "single GPU"},
         "roofline": roof,
         "roofline_classes": classes,

@@ -169,11 +169,13 @@ ifctn_status ifctn_assemble(const ifctn_params* params, const double* G_host, vo
 ifctn_status ifctn_assemble_noalloc(const ifctn_params* params, const double* G_host, void* out_dev,
                                     void* stream);
 
-/* Per-kernel timing with HIP events recorded on the job's stream around every
- * launch of the given kernel class (0 = mode-k contraction, 1 = factor-block
- * solve, 2 = X update, 3 = Gram weights).  enable = 1 starts a fresh tally, 0 stops.  The query
- * synchronises and returns the total milliseconds and launch count since the
- * tally started. */
+/* Per-kernel timing with HIP events stamped with the start and end of every
+ * launch of the given kernel class, on the stream it runs on (0 = mode-k
+ * contraction, 1 = factor-block solve, 2 = X update, 3 = Gram weights or the
+ * Gamma_k build, 4 = the U-row reduction of a Gamma-route block when Gamma_k
+ * is built on the job's second stream).  enable = 1 starts a fresh tally,
+ * 0 stops.  The query synchronises and returns the total milliseconds and
+ * launch count since the tally started; an unknown class: IFCTN_E_INVAL. */
 ifctn_status ifctn_timing_enable(ifctn_job* job, int32_t enable);
 ifctn_status ifctn_timing_query(ifctn_job* job, int32_t kernel_class, double* total_ms,
                                 int64_t* launches);

@@ -1056,7 +1056,7 @@ struct ifctn_job {
   double stop_eps = 0.0;
   bool timing = false;
   std::vector<hipEvent_t> ev[KC_COUNT];
-  size_t evn[KC_COUNT] = {0, 0, 0, 0};
+  size_t evn[KC_COUNT] = {};
 };
 
 namespace {
@@ -1506,7 +1506,7 @@ hipError_t run_sweep(ifctn_job* J) {
       if (e != hipSuccess) return e;
     }
     if (J->groute[k]) {              // Gamma_k and the U rows, then the solve
-      e = side ? timed(J, KC_GRAM, do_urow_join, &k) : timed(J, KC_GRAM, do_gamma, &k);
+      e = side ? timed(J, KC_UROW, do_urow_join, &k) : timed(J, KC_GRAM, do_gamma, &k);
       if (e != hipSuccess) return e;
     }
     e = timed(J, KC_SOLVE, do_solve, &J->splan[k]);

@@ -434,7 +434,7 @@ hipError_t launch_lr_solve(const LrSolveArgs& a, hipStream_t s);
 hipError_t launch_lr_x(int dtype, const LrXArgs& a, int nblk, hipStream_t s);
 
 // kernel classes for timing
-enum KernelClass { KC_CONTRACT = 0, KC_SOLVE = 1, KC_UPDATE = 2, KC_GRAM = 3, KC_COUNT = 4 };
+enum KernelClass { KC_CONTRACT = 0, KC_SOLVE = 1, KC_UPDATE = 2, KC_GRAM = 3, KC_UROW = 4, KC_COUNT = 5 };
 
 // ---- launchers (ifctn_kernels.hip) ----------------------------------------
 // dtype: 0 = float32 streaming data, 1 = float64

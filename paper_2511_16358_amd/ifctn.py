@@ -26,7 +26,7 @@ IFCTN_MAX_ORDER = 5
 IFCTN_MAX_RANK = 36
 IFCTN_OK, IFCTN_E_INVAL, IFCTN_E_NOMEM, IFCTN_E_HIP, IFCTN_E_STATE, IFCTN_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
 IFCTN_FP32, IFCTN_BF16_REFINE, IFCTN_FP64 = 0, 1, 2
-KC_CONTRACT, KC_SOLVE, KC_UPDATE, KC_GRAM = 0, 1, 2, 3
+KC_CONTRACT, KC_SOLVE, KC_UPDATE, KC_GRAM, KC_UROW = 0, 1, 2, 3, 4
 
 EXPORTED = [
     "ifctn_num_factor_entries", "ifctn_workspace_bytes", "ifctn_init", "ifctn_sweep",

@@ -3,6 +3,8 @@
     python -m paper_2511_16358_amd.profsum stats <run_kernel_stats.csv>
     python -m paper_2511_16358_amd.profsum traffic <fetch.csv> <write.csv> \
         <copy_fetch.csv> <copy_write.csv> <copy_bytes>
+    python -m paper_2511_16358_amd.profsum counters <run_counter_collection.csv>
+    python -m paper_2511_16358_amd.profsum grids <run_kernel_trace.csv> <kernel name part>
 
 `stats` prints the per-kernel call count and durations of a
 ``rocprofv3 --kernel-trace --stats --output-format csv`` run.  `traffic` turns
@@ -10,7 +12,9 @@ two ``--pmc FETCH_SIZE`` / ``--pmc WRITE_SIZE`` runs (KiB per dispatch) into
 bytes per launch, each counter scaled by what it reads for a plain device copy
 of ``copy_bytes`` bytes each way, and prints the per-launch HBM bytes of the
 contraction kernels in a line that bench.py reads back (valid only for the
-kernel sources whose digest it carries).
+kernel sources whose digest it carries).  `counters` prints the per-dispatch
+mean of every counter of a ``--pmc`` run, per kernel; `grids` splits the
+launches of one kernel of a kernel trace by workgroup count.
 """
 from __future__ import annotations
 
@@ -90,10 +94,46 @@ def traffic(fetch: str, write: str, cfetch: str, cwrite: str, copy_bytes: str) -
               f"hbm_bytes_per_launch={(tot_f + tot_w) / n_con:.0f} launches={n_con}")
 
 
+def grids(path: str, kernel: str) -> None:
+    """Launches of one kernel (name contains `kernel`) in a --kernel-trace run,
+    split by grid size: count and mean / min / max duration."""
+    per = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        if kernel in r["Kernel_Name"]:
+            per[int(r["Grid_Size_X"]) // max(1, int(r["Workgroup_Size_X"]))].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    print("%-40s %10s %6s %9s %9s %9s" % ("kernel", "workgroups", "calls", "avg_us", "min_us", "max_us"))
+    for wg in sorted(per):
+        v = per[wg]
+        print("%-40s %10d %6d %9.2f %9.2f %9.2f" % (kernel[:40], wg, len(v), sum(v) / len(v), min(v), max(v)))
+
+
+def counters(path: str) -> None:
+    """Per kernel: dispatch count and the mean of every counter of the run."""
+    per = collections.defaultdict(lambda: collections.defaultdict(list))
+    names = []
+    for r in csv.DictReader(open(path)):
+        c = r["Counter_Name"]
+        if c not in names:
+            names.append(c)
+        per[r["Kernel_Name"]][c].append(float(r["Counter_Value"]))
+    print("%-64s %5s " % ("kernel", "n") + " ".join("%14s" % c.replace("SQ_", "")[:14] for c in names))
+    order = sorted(per, key=lambda n: -sum(per[n][names[0]]) if per[n][names[0]] else 0)
+    for n in order:
+        cnt = max(len(v) for v in per[n].values())
+        vals = ["%14.0f" % (sum(per[n][c]) / len(per[n][c])) if per[n][c] else "%14s" % "-" for c in names]
+        short = _short(n)
+        print("%-64s %5d " % (short[:64], cnt) + " ".join(vals))
+
+
 if __name__ == "__main__":
-    if len(sys.argv) < 2 or sys.argv[1] not in ("stats", "traffic"):
+    if len(sys.argv) < 2 or sys.argv[1] not in ("stats", "traffic", "counters", "grids"):
         raise SystemExit(__doc__)
     if sys.argv[1] == "stats":
         stats(sys.argv[2])
+    elif sys.argv[1] == "grids":
+        grids(sys.argv[2], sys.argv[3])
+    elif sys.argv[1] == "counters":
+        counters(sys.argv[2])
     else:
         traffic(*sys.argv[2:7])
