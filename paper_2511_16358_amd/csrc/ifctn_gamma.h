@@ -209,13 +209,29 @@ __device__ __forceinline__ void gamma_block(const GammaPlan* __restrict__ gp, in
         const double* cqr = cq + (hasx ? (q0 + min(qq, nc - 1)) * Ky : 0);
         gm_d4 acc = {0.0, 0.0, 0.0, 0.0};
         for (int k0 = 0; k0 < Ky; k0 += 16) {
-          double av[4], bv[4];
+          // operands read at clamped indices, every read of the step issued
+          // before the first use; out-of-range terms are zeroed afterwards
+          double av[4], bv[4], b1v[4], b2v[4], b3v[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int yc = min(k0 + 4 * u + (lane >> 4), Ky - 1);
+            av[u] = arow[yc];
+            b1v[u] = g1[yc];
+            b2v[u] = g2[yc];
+            b3v[u] = hasx ? cqr[yc] : 1.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            av[u] = pin(av[u]);
+            b1v[u] = pin(b1v[u]);
+            b2v[u] = pin(b2v[u]);
+            b3v[u] = pin(b3v[u]);
+          }
 #pragma unroll
           for (int u = 0; u < 4; ++u) {
             const int y = k0 + 4 * u + (lane >> 4);
-            const int yc = min(y, Ky - 1);
-            av[u] = (aok && y < Ky) ? arow[yc] : 0.0;
-            bv[u] = (bok && y < Ky) ? g1[yc] * g2[yc] * (hasx ? cqr[yc] : 1.0) : 0.0;
+            av[u] = (aok && y < Ky) ? av[u] : 0.0;
+            bv[u] = (bok && y < Ky) ? b1v[u] * b2v[u] * b3v[u] : 0.0;
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u) acc = gm_mfma(av[u], bv[u], acc);
@@ -249,6 +265,13 @@ __device__ __forceinline__ void gamma_block(const GammaPlan* __restrict__ gp, in
             b[u] = g1[x];
             c[u] = g2[x];
             d[u] = tc[x * Ncol];
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            a[u] = pin(a[u]);
+            b[u] = pin(b[u]);
+            c[u] = pin(c[u]);
+            d[u] = pin(d[u]);
           }
 #pragma unroll
           for (int u = 0; u < 4; ++u)

@@ -173,12 +173,24 @@ __device__ __forceinline__ double ldlt_solve(const double* Hs, const double* bs,
 // new column, mult(p) x_r x_r' for the pairs p = {r <= r'} in packed order
 // (read by the later sub-blocks of the block).
 template <int R>
-__device__ __forceinline__ double ldlt_solve_pairs(const double* Hs, const double* bs, double rho,
-                                                   const double* gold, double* x_out, double* mg_out) {
-  const double dg = ldlt_solve<R>(Hs, bs, rho, gold, x_out);
-  double x[R];
+__device__ __forceinline__ double ldlt_solve_pairs(const double* hin, const double* bin, double rho, double* g,
+                                                   double* mg_out) {
+  // every input read from LDS in one batch into registers (the packed H_j,
+  // b_j and the old column), then the factorisation; g is overwritten with
+  // the new column and mg_out with its pair weights
+  constexpr int NP = R * (R + 1) / 2;
+  double hv[NP], bv[R], go[R];
 #pragma unroll
-  for (int r = 0; r < R; ++r) x[r] = x_out[r];
+  for (int p = 0; p < NP; ++p) hv[p] = hin[p];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    go[r] = g[r];
+    bv[r] = bin[r] + rho * go[r];
+  }
+  double x[R];
+  const double dg = ldlt_solve<R>(hv, bv, rho, go, x);
+#pragma unroll
+  for (int r = 0; r < R; ++r) g[r] = x[r];
   int p = 0;
 #pragma unroll
   for (int r = 0; r < R; ++r)
@@ -441,6 +453,12 @@ __device__ __forceinline__ void chain_stage(const double* __restrict__ in, doubl
         b1[u] = in[off1 + q * sc];
       }
 #pragma unroll
+      for (int u = 0; u < 8; ++u) {     // the batch's reads all issued before the first use
+        a[u] = pin(a[u]);
+        b0[u] = pin(b0[u]);
+        b1[u] = pin(b1[u]);
+      }
+#pragma unroll
       for (int u = 0; u < 8; ++u)
         if (q0 + u < dc) {
           s0 += a[u] * b0[u];
@@ -471,9 +489,6 @@ __global__ __launch_bounds__(NT) void k_solve_gamma(const GSolve* __restrict__ g
   double* h2 = h1 + scr;
   double* b1 = h2 + scr;                 // b chain buffers
   double* b2 = b1 + scr;
-  double* Hs = b2 + scr;
-  double* bs = Hs + MAXP;
-  double* gold = bs + MAXR;
   double* gik = wbase + wd;              // far-side factors (when staged)
   const bool gl = gs->gik_lds != 0;
   int* tab = (int*)(gik + (gl ? gs->gik_tot : 0));
@@ -558,21 +573,16 @@ __global__ __launch_bounds__(NT) void k_solve_gamma(const GSolve* __restrict__ g
       // later sub-blocks
       double* gt = g + t * MAXR;
       double* mt = mg + t * MAXP;
-      for (int p = 0; p < gs->np[t]; ++p) Hs[p] = hin[p];
-      for (int r = 0; r < R; ++r) {
-        gold[r] = gt[r];
-        bs[r] = bin[r] + gs->rho * gt[r];
-      }
       double dg = 0.0;
       switch (R) {
-        case 1: dg = ldlt_solve_pairs<1>(Hs, bs, gs->rho, gold, gt, mt); break;
-        case 2: dg = ldlt_solve_pairs<2>(Hs, bs, gs->rho, gold, gt, mt); break;
-        case 3: dg = ldlt_solve_pairs<3>(Hs, bs, gs->rho, gold, gt, mt); break;
-        case 4: dg = ldlt_solve_pairs<4>(Hs, bs, gs->rho, gold, gt, mt); break;
-        case 5: dg = ldlt_solve_pairs<5>(Hs, bs, gs->rho, gold, gt, mt); break;
-        case 6: dg = ldlt_solve_pairs<6>(Hs, bs, gs->rho, gold, gt, mt); break;
-        case 7: dg = ldlt_solve_pairs<7>(Hs, bs, gs->rho, gold, gt, mt); break;
-        default: dg = ldlt_solve_pairs<8>(Hs, bs, gs->rho, gold, gt, mt); break;
+        case 1: dg = ldlt_solve_pairs<1>(hin, bin, gs->rho, gt, mt); break;
+        case 2: dg = ldlt_solve_pairs<2>(hin, bin, gs->rho, gt, mt); break;
+        case 3: dg = ldlt_solve_pairs<3>(hin, bin, gs->rho, gt, mt); break;
+        case 4: dg = ldlt_solve_pairs<4>(hin, bin, gs->rho, gt, mt); break;
+        case 5: dg = ldlt_solve_pairs<5>(hin, bin, gs->rho, gt, mt); break;
+        case 6: dg = ldlt_solve_pairs<6>(hin, bin, gs->rho, gt, mt); break;
+        case 7: dg = ldlt_solve_pairs<7>(hin, bin, gs->rho, gt, mt); break;
+        default: dg = ldlt_solve_pairs<8>(hin, bin, gs->rho, gt, mt); break;
       }
       gs->dgpart[(long long)t * Ik + j] = dg;
     }
