@@ -291,7 +291,9 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
     {
       const int y = min(tid, B.Ii - 1);
 #pragma unroll
-      for (int r = 0; r < MAXR; ++r) gpre[r] = r < R ? Gik[(long long)r * B.Ii + y] : 0.0;
+      for (int r = 0; r < MAXR; ++r) gpre[r] = Gik[(long long)min(r, R - 1) * B.Ii + y];   // in bounds
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) gpre[r] = r < R ? pin(gpre[r]) : 0.0;
     }
     // H_j partials: thread (p, c) sums d = c mod cpp.  Per d-tile, the
     // weights w_j(d) = prod_{m in d} W_{k,m}(j, i_m)^2 are formed once in LDS;
@@ -322,10 +324,18 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
       }
       __syncthreads();
       if (c_me < cpp) {
+        double wv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) wv[u] = wl[min(c_me + u * cpp, nd_t - 1)];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          wv[u] = pin(wv[u]);
+          qv[u] = pin(qv[u]);
+        }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
           const int e = c_me + u * cpp;
-          if (e < nd_t) hacc += wl[e] * qv[u];
+          if (e < nd_t) hacc += wv[u] * qv[u];
         }
         // the rest of this thread's d (c_me + u cpp, u >= 8), ascending
         const int e8 = c_me + 8 * cpp;
@@ -395,13 +405,25 @@ __global__ __launch_bounds__(NT) void k_solve(SolveArgs a) {
 
     // row j of W_{k,i} from the new column: LDS copy for the next i, HBM for later blocks
     for (int y = tid; y < B.Ii; y += NT) {
-      double gv[MAXR];
+      double gv[MAXR], gn[MAXR];
+      if (y < NT) {
 #pragma unroll
-      for (int r = 0; r < MAXR; ++r) gv[r] = y < NT ? gpre[r] : (r < R ? Gik[(long long)r * B.Ii + y] : 0.0);
+        for (int r = 0; r < MAXR; ++r) gv[r] = gpre[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < MAXR; ++r) gv[r] = Gik[(long long)min(r, R - 1) * B.Ii + y];   // in bounds
+      }
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) gn[r] = gnew[r];
+#pragma unroll
+      for (int r = 0; r < MAXR; ++r) {
+        gv[r] = pin(gv[r]);
+        gn[r] = pin(gn[r]);
+      }
       double sum = 0.0;
 #pragma unroll
       for (int r = 0; r < MAXR; ++r)
-        if (r < R) sum += gnew[r] * gv[r];
+        if (r < R) sum += gn[r] * gv[r];
       rows[a.rowoff[B.upos] + y] = sum;
       const long long ad = B.w_off + (long long)j * B.w_sj + (long long)y * B.w_sy;
       a.W64[ad] = sum;
