@@ -289,12 +289,33 @@ __device__ __forceinline__ void gamma_block(const GammaPlan* __restrict__ gp, in
       if (tile < AMT * ANT) {
         const int mt = tile / ANT, nt = tile - mt * ANT;
         const int row = mt * 16 + (lane & 15), col = nt * 16 + (lane & 15);
-        for (int k0 = 0; k0 < nc; k0 += 4) {
-          const int k = k0 + (lane >> 4);
-          const bool kok = k < nc;
-          const double a = (kok && row < npp) ? cp[(q0 + k) * npp + row] : 0.0;
-          const double b = (kok && col < NYw) ? (n >= 2 ? Ys[k * NYw + col] : 1.0) : 0.0;
-          V[v] = gm_mfma(a, b, V[v]);
+        const int rowc = min(row, npp - 1), colc = min(col, NYw - 1);
+        // four matrix-core steps per batch of operand reads (clamped
+        // indices, all reads in flight before the first step; terms out of
+        // range zeroed), k in the same order as one step at a time
+        for (int k0 = 0; k0 < nc; k0 += 16) {
+          double av[4], bv[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int kc = min(k0 + 4 * u + (lane >> 4), nc - 1);
+            av[u] = cp[(q0 + kc) * npp + rowc];
+            bv[u] = n >= 2 ? Ys[kc * NYw + colc] : 1.0;
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            av[u] = pin(av[u]);
+            bv[u] = pin(bv[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            const int k = k0 + 4 * u + (lane >> 4);
+            if (k0 + 4 * u < nc) {        // uniform: the step has at least one k in range
+              const bool kok = k < nc;
+              const double a = (kok && row < npp) ? av[u] : 0.0;
+              const double b = (kok && col < NYw) ? bv[u] : 0.0;
+              V[v] = gm_mfma(a, b, V[v]);
+            }
+          }
         }
       }
     }
@@ -336,6 +357,10 @@ __device__ __forceinline__ void gamma_block(const GammaPlan* __restrict__ gp, in
 #pragma unroll
       for (int q = 0; q < GM_QG; ++q) vv[h][q] = part[(long long)min(q, nqg - 1) * P + gi];
     }
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+      for (int q = 0; q < GM_QG; ++q) vv[h][q] = pin(vv[h][q]);
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
       double s = 0.0;
