@@ -660,6 +660,7 @@ bool plan_gamma(const Geo& g, int k, GammaPlan* gp) {
   gp->qpw = (int)qpw;
   gp->nqg = (int)cdiv(gp->nq, qpw);
   gp->nyg = nyg;
+  gp->nred = gp->nqg > 1 ? (int)cdiv(gp->P, 4 * NT) : 0;
   gp->pyw = pyw;
   gp->nw = gp->nyg * gp->nqg;
   return true;
@@ -1388,12 +1389,12 @@ hipError_t do_gamma_side(ifctn_job* J, const void* c) {
   return e;
 }
 
-// the U rows of block k on the job's stream (after the contraction), then the
-// wait for Gamma_k
+// the wait for Gamma_k, then on the job's stream (after the contraction) the
+// U rows of block k and the sum of Gamma_k's partial rows
 hipError_t do_urow_join(ifctn_job* J, const void* c) {
   const int k = *(const int*)c;
-  hipError_t e = launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream, 2);
-  if (e == hipSuccess) e = hipStreamWaitEvent(J->stream, J->ev_join, 0);
+  hipError_t e = hipStreamWaitEvent(J->stream, J->ev_join, 0);
+  if (e == hipSuccess) e = launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream, 2);
   return e;
 }
 
@@ -1794,6 +1795,7 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
     while (gp.us < 64 && (long long)gp.us * 8 < gp.S) gp.us *= 2;
     gp.nuw = (int)cdiv(gp.nout, NT / gp.us);
     gp.Ufin = J->Ufin;
+    gp.sepred = opts.overlap ? 1 : 0;   // Gamma_k on the second stream: summed after the join
     GSolve& gs = J->gsol[k];
     gs.S = 1;                        // the U rows arrive reduced (Ufin)
     gs.Upart = J->Ufin;

@@ -45,6 +45,34 @@ __device__ __forceinline__ gm_d4 gm_mfma(double a, double b, gm_d4 c) {
 // workgroup, each summed by US slices of the slots (slot order within a
 // slice), then the slices in slice order (a fixed order: bitwise
 // reproducible).
+// Gamma_k(e) = sum over the nqg prefix ranges of their partial rows, in range
+// order (the order of the in-launch last-workgroup sum), four entries per
+// thread with all their loads in flight; workgroup b covers 4 NT entries.
+__device__ __forceinline__ void gamma_reduce_block(const GammaPlan* __restrict__ gp, int b) {
+  const int P = gp->P, nqg = gp->nqg;
+  const double* part = gp->part;
+  const int e0 = b * 4 * NT + (int)threadIdx.x;
+  double vv[4][GM_QG];
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    const int e = min(e0 + h * NT, P - 1);
+#pragma unroll
+    for (int q = 0; q < GM_QG; ++q) vv[h][q] = part[(long long)min(q, nqg - 1) * P + e];
+  }
+#pragma unroll
+  for (int h = 0; h < 4; ++h)
+#pragma unroll
+    for (int q = 0; q < GM_QG; ++q) vv[h][q] = pin(vv[h][q]);
+#pragma unroll
+  for (int h = 0; h < 4; ++h) {
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < GM_QG; ++q)
+      if (q < nqg) s += vv[h][q];
+    if (e0 + h * NT < P) gp->gamma[e0 + h * NT] = s;
+  }
+}
+
 __device__ __forceinline__ void urow_block(const GammaPlan* __restrict__ gp, int b) {
   __shared__ double ured[NT];
   const int tid = threadIdx.x, US = gp->us, UO = NT / US;
@@ -340,7 +368,7 @@ __device__ __forceinline__ void gamma_block(const GammaPlan* __restrict__ gp, in
       }
     }
   }
-  if (nqg == 1) return;
+  if (nqg == 1 || gp->sepred) return;   // sepred: summed by gamma_reduce_block
   double* part = gp->part;
   // the last of the y group's workgroups adds the nqg partial sums (prefix-range order)
   __threadfence();

@@ -118,6 +118,10 @@ struct GammaPlan {
   // the U rows: nuw workgroups after the nw Gamma workgroups, NT / us outputs
   // each, every output summed in us slices of the S slots
   int nuw, S, us;
+  // sepred: the partial rows of Gamma_k are summed by nred workgroups of the
+  // U-row launch (after the Gamma_k launch), not by the last workgroup of
+  // each group inside it
+  int nred, sepred;
   long long nout;               // I_k * Rprod
   const double* Upart;          // [S][nout]
   double* Ufin;                 // [nout]

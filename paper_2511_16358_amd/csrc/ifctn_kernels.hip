@@ -450,8 +450,10 @@ __global__ __launch_bounds__(NT) void k_gamma(const GammaPlan* __restrict__ gp, 
   const int b = (int)blockIdx.x + b0, nw = gp->nw;
   if (b < nw)
     gamma_block<GM_VPT>(gp, b);
-  else
+  else if (b < nw + gp->nuw)
     urow_block(gp, b - nw);
+  else
+    gamma_reduce_block(gp, b - nw - gp->nuw);
 }
 
 // One stage of a contraction chain: out[o] = sum_q v[q] in[tab[o] + q sc].
@@ -1149,7 +1151,9 @@ hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* sto
     if (e != hipSuccess) return e;
   }
   const int b0 = part == 2 ? hp.nw : 0;
-  const int nb = part == 1 ? hp.nw : part == 2 ? hp.nuw : hp.nw + hp.nuw;
+  const int nred = hp.sepred ? hp.nred : 0;
+  // the partial-row sum (sepred) must follow the Gamma_k launch: part 2 only
+  const int nb = part == 1 ? hp.nw : part == 2 ? hp.nuw + nred : hp.nw + hp.nuw;
   if (nb <= 0) return hipSuccess;
   IFCTN_GO(k_gamma, dim3((unsigned)nb), dim3(NT), (size_t)hp.smem, s, gm, stop, b0);
   return hipGetLastError();
