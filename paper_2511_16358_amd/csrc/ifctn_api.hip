@@ -1039,7 +1039,6 @@ struct ifctn_job {
   std::vector<int> htab;       // host copy of the Gamma-route offset tables (source of an async copy)
   double* gamma = nullptr;
   double* gmpart = nullptr;
-  int* gmcnt = nullptr;
   bool merge[MAXN] = {};       // Gram weights inside the contraction launch
   PhaseArgs pplan[MAXN][MAXN - 1];
   int nnorm = 0, ndg = 0;
@@ -1064,14 +1063,14 @@ namespace {
 
 struct Sizes {
   size_t x, xb, bits, G, W64, Wc, Q, Upart, Ugrp, ucnt, Ufin, Hpart, hcnt, normpart, dgpart, stats, flag, qitems;
-  size_t gamma, gmpart, gmcnt, grec, gtab;
+  size_t gamma, gmpart, grec, gtab;
   size_t lr0, lr1, lrc, lrh;   // large-rank route: Y / mode-product buffers, c weights, packed H rows
   size_t total;
 };
 
 size_t sizes_total(const Sizes& s) {
   return s.x + s.xb + s.bits + s.G + s.W64 + s.Wc + s.Q + s.Upart + s.Ugrp + s.ucnt + s.Ufin + s.Hpart + s.hcnt +
-         s.normpart + s.dgpart + s.stats + s.flag + s.qitems + s.gamma + s.gmpart + s.gmcnt + s.grec + s.gtab +
+         s.normpart + s.dgpart + s.stats + s.flag + s.qitems + s.gamma + s.gmpart + s.grec + s.gtab +
          s.lr0 + s.lr1 + s.lrc + s.lrh;
 }
 
@@ -1135,7 +1134,7 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o, Ga
   s.W64 = al256(g.nW * 8);
   s.Wc = al256(g.nW * g.esz);
   long long qmax = 0, upmax = 0, ugmax = 0, ucmax = 0, ufmax = 0, hmax = 0, nnorm = 0, ndg = 0;
-  long long gmP = 0, gmpart = 0, gmcnt = 0, gtab = 0;
+  long long gmP = 0, gmpart = 0, gtab = 0;
   const bool dbg = std::getenv("IFCTN_DEBUG_PLAN") != nullptr;
   for (int k = 0; k < g.N; ++k) {
     ContractPlan P = plan_contract(g, k, o);
@@ -1170,7 +1169,6 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o, Ga
       if (gsl) gsl[k] = gsk;
       gmP = std::max<long long>(gmP, gpk.P);
       gmpart = std::max<long long>(gmpart, (long long)gpk.nqg * gpk.P);
-      gmcnt = std::max<long long>(gmcnt, gpk.nyg);
       gtab += gsk.tabtot;
       qs = 0;                        // no Gram weight sets for this block
     }
@@ -1203,7 +1201,6 @@ Sizes job_sizes(const Geo& g, ContractPlan* cp, QArgs* qp, const PlanOpts& o, Ga
   s.qitems = al256(sizeof(QItem) * MAXN * (MAXN - 1));
   s.gamma = al256(gmP * 8);
   s.gmpart = al256(gmpart * 8);
-  s.gmcnt = al256(gmcnt * 4);
   s.grec = al256(sizeof(GammaPlan) * MAXN) + al256(sizeof(GSolve) * MAXN);
   s.gtab = al256(gtab * 4);
   s.total = sizes_total(s);
@@ -1374,7 +1371,11 @@ hipError_t do_gram(ifctn_job* J, const void* c) { return launch_q(*(const QArgs*
 
 hipError_t do_gamma(ifctn_job* J, const void* c) {
   const int k = *(const int*)c;
-  return launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream, 0);
+  const GammaPlan& gp = J->gplan[k];
+  // Gamma_k, then the U rows and the sum of its partial rows
+  hipError_t e = launch_gamma(gp, J->dgp + k, J->flag + 1, J->stream, 1);
+  if (e == hipSuccess) e = launch_gamma(gp, J->dgp + k, J->flag + 1, J->stream, 2);
+  return e;
 }
 
 // Gamma_k on the side stream, after everything enqueued on the job's stream
@@ -1739,7 +1740,6 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   QItem* dq = (QItem*)p;         p += s.qitems;
   J->gamma = (double*)p;         p += s.gamma;
   J->gmpart = (double*)p;        p += s.gmpart;
-  J->gmcnt = (int*)p;            p += s.gmcnt;
   J->dgp = (GammaPlan*)p;        p += al256(sizeof(GammaPlan) * MAXN);
   J->dgs = (GSolve*)p;           p += al256(sizeof(GSolve) * MAXN);
   int* dtab = (int*)p;           p += s.gtab;
@@ -1785,7 +1785,6 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
     gp.G = J->G;
     gp.part = J->gmpart;
     gp.gamma = J->gamma;
-    gp.cnt = J->gmcnt;
     const ContractArgs& ca = J->cplan[k].a;
     gp.S = ca.ugrp ? ca.ngrp : ca.S * ca.FS;
     gp.Upart = ca.ugrp ? J->Ugrp : J->Upart;
@@ -1795,7 +1794,6 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
     while (gp.us < 64 && (long long)gp.us * 8 < gp.S) gp.us *= 2;
     gp.nuw = (int)cdiv(gp.nout, NT / gp.us);
     gp.Ufin = J->Ufin;
-    gp.sepred = opts.overlap ? 1 : 0;   // Gamma_k on the second stream: summed after the join
     GSolve& gs = J->gsol[k];
     gs.S = 1;                        // the U rows arrive reduced (Ufin)
     gs.Upart = J->Ufin;
@@ -1856,7 +1854,6 @@ ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8
   INIT_TRY(hipMemsetAsync(J->flag, 0, s.flag, J->stream));
   INIT_TRY(hipMemsetAsync(J->hcnt, 0, s.hcnt, J->stream));
   INIT_TRY(hipMemsetAsync(J->ucnt, 0, s.ucnt, J->stream));
-  INIT_TRY(hipMemsetAsync(J->gmcnt, 0, s.gmcnt, J->stream));
   INIT_TRY(hipMemcpyAsync(J->dgp, J->gplan, sizeof(GammaPlan) * MAXN, hipMemcpyHostToDevice, J->stream));
   INIT_TRY(hipMemcpyAsync(J->dgs, J->gsol, sizeof(GSolve) * MAXN, hipMemcpyHostToDevice, J->stream));
   if (!htab.empty())

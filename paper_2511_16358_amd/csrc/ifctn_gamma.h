@@ -97,7 +97,6 @@ __device__ __forceinline__ void urow_block(const GammaPlan* __restrict__ gp, int
 template <int VPT>
 __device__ __forceinline__ void gamma_block(const GammaPlan* __restrict__ gp, int w) {
   extern __shared__ __attribute__((aligned(16))) unsigned char gm_smem[];
-  __shared__ int gm_last;
   double* sm = (double*)gm_smem;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int n = gp->n, npre = gp->npre, hasx = gp->hasx;
@@ -368,37 +367,7 @@ __device__ __forceinline__ void gamma_block(const GammaPlan* __restrict__ gp, in
       }
     }
   }
-  if (nqg == 1 || gp->sepred) return;   // sepred: summed by gamma_reduce_block
-  double* part = gp->part;
-  // the last of the y group's workgroups adds the nqg partial sums (prefix-range order)
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) gm_last = atomicAdd(&gp->cnt[yg], 1) == nqg - 1 ? 1 : 0;
-  __syncthreads();
-  if (!gm_last) return;
-  __threadfence();
-  for (int e0 = tid; e0 < Pw; e0 += 4 * NT) {     // four entries, all their loads in flight
-    double vv[4][GM_QG];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      const int gi = gidx(min(e0 + h * NT, Pw - 1));
-#pragma unroll
-      for (int q = 0; q < GM_QG; ++q) vv[h][q] = part[(long long)min(q, nqg - 1) * P + gi];
-    }
-#pragma unroll
-    for (int h = 0; h < 4; ++h)
-#pragma unroll
-      for (int q = 0; q < GM_QG; ++q) vv[h][q] = pin(vv[h][q]);
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-      double s = 0.0;
-#pragma unroll
-      for (int q = 0; q < GM_QG; ++q)
-        if (q < nqg) s += vv[h][q];
-      if (e0 + h * NT < Pw) gp->gamma[gidx(e0 + h * NT)] = s;
-    }
-  }
-  if (tid == 0) gp->cnt[yg] = 0;        // ready for the next launch (stream order)
+  // with nqg > 1 the partial rows are summed by gamma_reduce_block in the next launch
 }
 
 }  // namespace ifctn

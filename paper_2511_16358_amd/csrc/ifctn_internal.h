@@ -102,7 +102,7 @@ struct GammaPlan {
   int qpw, nqc;                 // prefix tuples per workgroup, per LDS chunk
   // workgroup w = (y group w % nyg, prefix range w / nyg): the y pair
   // indices [yg * pyw, +pyw) of Gamma over prefix tuples [qg * qpw, +qpw);
-  // the nqg partial sums of a y group are added by its last workgroup
+  // with nqg > 1 the partial rows are summed by the next launch
   int nyg, pyw, nqg;
   int nw;                       // nyg * nqg
   double fma;                   // multiply-adds of the build (stage A + B + accumulation)
@@ -113,15 +113,12 @@ struct GammaPlan {
   const double* G;
   double* part;                 // [nqg][P] partial sums (each y group writes its entries)
   double* gamma;                // [P]
-  int* cnt;                     // [nyg] arrival counters, zero between launches
-  // the same launch reduces the contraction's partial slots of block k into
-  // the U rows: nuw workgroups after the nw Gamma workgroups, NT / us outputs
-  // each, every output summed in us slices of the S slots
+  // the launch after Gamma_k's (and after the contraction of block k): nuw
+  // workgroups reduce the contraction's partial slots into the U rows (NT / us
+  // outputs each, every output summed in us slices of the S slots), then nred
+  // workgroups sum the nqg partial rows of Gamma_k
   int nuw, S, us;
-  // sepred: the partial rows of Gamma_k are summed by nred workgroups of the
-  // U-row launch (after the Gamma_k launch), not by the last workgroup of
-  // each group inside it
-  int nred, sepred;
+  int nred;
   long long nout;               // I_k * Rprod
   const double* Upart;          // [S][nout]
   double* Ufin;                 // [nout]
@@ -463,8 +460,8 @@ void set_kernel_events(hipEvent_t start, hipEvent_t stop);
 bool kernel_events_used();
 hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s);
 // Gamma route: Gamma_k in a launch of its own (gm: device copy of hp), and the solve
-// part 0: both roles; 1: Gamma_k only (no dependence on X or U_k); 2: the U
-// rows only (after the contraction of block k)
+// part 1: Gamma_k (no dependence on X or U_k); part 2, after it and after the
+// contraction of block k: the U rows and the sum of Gamma_k's partial rows
 hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* stop, hipStream_t s, int part);
 hipError_t launch_solve_gamma(int dtype, const GSolve& hs, const GSolve* gs, hipStream_t s);
 size_t solve_smem_bytes(const SolveArgs& a);

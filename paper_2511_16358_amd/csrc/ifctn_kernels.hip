@@ -1151,9 +1151,7 @@ hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* sto
     if (e != hipSuccess) return e;
   }
   const int b0 = part == 2 ? hp.nw : 0;
-  const int nred = hp.sepred ? hp.nred : 0;
-  // the partial-row sum (sepred) must follow the Gamma_k launch: part 2 only
-  const int nb = part == 1 ? hp.nw : part == 2 ? hp.nuw + nred : hp.nw + hp.nuw;
+  const int nb = part == 1 ? hp.nw : hp.nuw + hp.nred;
   if (nb <= 0) return hipSuccess;
   IFCTN_GO(k_gamma, dim3((unsigned)nb), dim3(NT), (size_t)hp.smem, s, gm, stop, b0);
   return hipGetLastError();
