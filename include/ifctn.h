@@ -301,10 +301,11 @@ ifctn_status ifctn_plan_blocks(const ifctn_params* params, ifctn_block_plan* out
 ifctn_status ifctn_set_option(const char* name, int64_t value);
 /*   "gamma": factor-block route -- 1 (default): the Gamma route for blocks
  *   that would otherwise take the phased form, 0: never, 2: wherever it fits.
- *   "overlap": 1 (default): a job with Gamma-route blocks builds Gamma_k on
- *   a second stream of its own (default priority), concurrently with the
- *   mode-k contraction, joined by an event before the solve; 0: in line on
- *   the job's stream.  Jobs of a server always build it in line.
+ *   "overlap": 1 (default): in a job with Gamma-route blocks the mode-k
+ *   contraction runs on a second stream of the job's own (default
+ *   priority), concurrently with the Gamma_k build on the job's stream, and
+ *   is joined by an event before the solve; 0: everything in line on the
+ *   job's stream.  Jobs of a server always run in line.
  *   "ugroup": the contraction's partial slots are summed in groups of this
  *   many by the last workgroup of each group (default 0: off).
  *   "inject_admit_failures": the next `value` server admissions fail with

@@ -1042,8 +1042,8 @@ struct ifctn_job {
   bool merge[MAXN] = {};       // Gram weights inside the contraction launch
   PhaseArgs pplan[MAXN][MAXN - 1];
   int nnorm = 0, ndg = 0;
-  // Gamma route with overlap: Gamma_k is built on `side`, forked from and
-  // joined back into `stream` by the two events
+  // Gamma route with overlap: the mode-k contraction runs on `side`, forked
+  // from and joined back into `stream` (where Gamma_k is built) by the events
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool lr = false;             // large-rank route for every block (an edge rank above MAXR)
@@ -1378,19 +1378,13 @@ hipError_t do_gamma(ifctn_job* J, const void* c) {
   return e;
 }
 
-// Gamma_k on the side stream, after everything enqueued on the job's stream
-// so far (the previous block's solve): it reads only factors and edge
-// matrices that are final before block k, not X or U_k
-hipError_t do_gamma_side(ifctn_job* J, const void* c) {
+// Gamma_k on the job's stream (the contraction runs on the second one)
+hipError_t do_gamma_main(ifctn_job* J, const void* c) {
   const int k = *(const int*)c;
-  hipError_t e = hipEventRecord(J->ev_fork, J->stream);
-  if (e == hipSuccess) e = hipStreamWaitEvent(J->side, J->ev_fork, 0);
-  if (e == hipSuccess) e = launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->side, 1);
-  if (e == hipSuccess) e = hipEventRecord(J->ev_join, J->side);
-  return e;
+  return launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream, 1);
 }
 
-// the wait for Gamma_k, then on the job's stream (after the contraction) the
+// the wait for the contraction, then on the job's stream (after Gamma_k) the
 // U rows of block k and the sum of Gamma_k's partial rows
 hipError_t do_urow_join(ifctn_job* J, const void* c) {
   const int k = *(const int*)c;
@@ -1495,20 +1489,29 @@ hipError_t run_sweep(ifctn_job* J) {
       e = timed(J, KC_GRAM, do_gram, &J->qplan[k]);
       if (e != hipSuccess) return e;
     }
-    const bool side = J->groute[k] && J->side;
-    if (side) {
-      e = timed(J, KC_GRAM, do_gamma_side, &k);
-      if (e != hipSuccess) return e;
-    }
+    // Gamma route with overlap: the contraction (and stop test) forked onto
+    // the job's second stream, Gamma_k launched on the job's stream right
+    // after it -- launched first on its own queue, Gamma_k's few workgroups
+    // take their CUs before the contraction's fill the rest
+    const bool swap = J->groute[k] && J->side;
     ContractCall cc{k, k == 0 && J->pending, true};
-    e = timed(J, KC_CONTRACT, do_contract, &cc);
-    if (e != hipSuccess) return e;
-    if (cc.upd && J->dev_stop) {
-      e = launch_stop_test(J->normpart, J->nnorm, J->stop_eps, J->flag + 1, J->stream);
+    if (swap) {
+      e = hipEventRecord(J->ev_fork, J->stream);
+      if (e == hipSuccess) e = hipStreamWaitEvent(J->side, J->ev_fork, 0);
       if (e != hipSuccess) return e;
+      std::swap(J->stream, J->side);
     }
+    e = timed(J, KC_CONTRACT, do_contract, &cc);
+    if (e == hipSuccess && cc.upd && J->dev_stop)
+      e = launch_stop_test(J->normpart, J->nnorm, J->stop_eps, J->flag + 1, J->stream);
+    if (swap) {
+      std::swap(J->stream, J->side);
+      if (e == hipSuccess) e = hipEventRecord(J->ev_join, J->side);
+      if (e == hipSuccess) e = timed(J, KC_GRAM, do_gamma_main, &k);
+    }
+    if (e != hipSuccess) return e;
     if (J->groute[k]) {              // Gamma_k and the U rows, then the solve
-      e = side ? timed(J, KC_UROW, do_urow_join, &k) : timed(J, KC_GRAM, do_gamma, &k);
+      e = swap ? timed(J, KC_UROW, do_urow_join, &k) : timed(J, KC_GRAM, do_gamma, &k);
       if (e != hipSuccess) return e;
     }
     e = timed(J, KC_SOLVE, do_solve, &J->splan[k]);

@@ -17,7 +17,7 @@ struct PlanOpts {
   long long ugroup;   // partial slots per group of the contraction's grouped reduction (0 = off)
   bool merge_gram, onelaunch;
   int gamma;          // Gamma route: 0 never, 1 where the block would otherwise be phased, 2 wherever it fits
-  bool overlap;       // Gamma route: build Gamma_k on a second stream, concurrent with the contraction
+  bool overlap;       // Gamma route: the contraction on a second stream, concurrent with Gamma_k
 };
 PlanOpts current_opts();
 
