@@ -456,41 +456,44 @@ __global__ __launch_bounds__(NT) void k_gamma(const GammaPlan* __restrict__ gp, 
     gamma_reduce_block(gp, b - nw - gp->nuw);
 }
 
-// One stage of a contraction chain: out[o] = sum_q v[q] in[tab[o] + q sc].
-// Two outputs per thread at a time (the workgroup's threads over the
-// outputs), eight terms per batch of loads (all of a batch in flight before
-// the first product), terms added in ascending q.
-__device__ __forceinline__ void chain_stage(const double* __restrict__ in, double* __restrict__ out,
-                                            const int* __restrict__ tab, int nout, const double* __restrict__ v,
-                                            int dc, int sc, int lane) {
-  for (int o0 = lane; o0 < nout; o0 += 2 * NT) {
-    const int o1 = min(o0 + NT, nout - 1);
-    const int off0 = tab[o0], off1 = tab[o1];
-    double s0 = 0.0, s1 = 0.0;
+// One stage of the H chain and one of the b chain side by side: the
+// workgroup's threads take the H outputs first, then the b outputs, one
+// output each per pass, so both chains' reads are in flight together; each
+// output sums its terms in ascending q (eight reads per batch).
+struct ChainRef {
+  const double* in;
+  double* out;
+  const int* tab;
+  const double* v;
+  int nout, dc, sc;
+};
+
+__device__ __forceinline__ void chain_pair(const ChainRef& h, const ChainRef& b, int lane) {
+  const int tot = h.nout + b.nout;
+  for (int o = lane; o < tot; o += NT) {
+    const bool isH = o < h.nout;
+    const ChainRef& c = isH ? h : b;
+    const int oo = isH ? o : o - h.nout;
+    const int off = c.tab[oo], dc = c.dc, sc = c.sc;
+    double s = 0.0;
     for (int q0 = 0; q0 < dc; q0 += 8) {
-      double a[8], b0[8], b1[8];
+      double a[8], x[8];
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         const int q = min(q0 + u, dc - 1);
-        a[u] = v[q];
-        b0[u] = in[off0 + q * sc];
-        b1[u] = in[off1 + q * sc];
+        a[u] = c.v[q];
+        x[u] = c.in[off + q * sc];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {     // the batch's reads all issued before the first use
+      for (int u = 0; u < 8; ++u) {
         a[u] = pin(a[u]);
-        b0[u] = pin(b0[u]);
-        b1[u] = pin(b1[u]);
+        x[u] = pin(x[u]);
       }
 #pragma unroll
       for (int u = 0; u < 8; ++u)
-        if (q0 + u < dc) {
-          s0 += a[u] * b0[u];
-          s1 += a[u] * b1[u];
-        }
+        if (q0 + u < dc) s += a[u] * x[u];
     }
-    out[o0] = s0;
-    if (o0 + NT < nout) out[o0 + NT] = s1;
+    c.out[oo] = s;
   }
 }
 
@@ -585,8 +588,9 @@ __global__ __launch_bounds__(NT) void k_solve_gamma(const GSolve* __restrict__ g
       const int uh = gs->ord[t][c], ub = gs->bord[t][c];
       double* hout = (c & 1) ? h2 : h1;
       double* bout = (c & 1) ? b2 : b1;
-      chain_stage(hin, hout, tab + gs->hoff[t][c], gs->hnout[t][c], mg + uh * MAXP, gs->np[uh], gs->hsc[t][c], tid);
-      chain_stage(bin, bout, tab + gs->boff[t][c], gs->bnout[t][c], g + ub * MAXR, gs->R[ub], gs->bsc[t][c], tid);
+      const ChainRef hc{hin, hout, tab + gs->hoff[t][c], mg + uh * MAXP, gs->hnout[t][c], gs->np[uh], gs->hsc[t][c]};
+      const ChainRef bc{bin, bout, tab + gs->boff[t][c], g + ub * MAXR, gs->bnout[t][c], gs->R[ub], gs->bsc[t][c]};
+      chain_pair(hc, bc, tid);
       hin = hout;
       bin = bout;
       __syncthreads();
