@@ -1378,19 +1378,22 @@ hipError_t do_gamma(ifctn_job* J, const void* c) {
   return e;
 }
 
-// Gamma_k on the job's stream (the contraction runs on the second one)
+// Gamma_k, then the sum of its partial rows, on the job's stream (the
+// contraction runs on the second one)
 hipError_t do_gamma_main(ifctn_job* J, const void* c) {
   const int k = *(const int*)c;
   return launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream, 1);
 }
 
-// the wait for the contraction, then on the job's stream (after Gamma_k) the
-// U rows of block k and the sum of Gamma_k's partial rows
-hipError_t do_urow_join(ifctn_job* J, const void* c) {
+hipError_t do_gsum_main(ifctn_job* J, const void* c) {
   const int k = *(const int*)c;
-  hipError_t e = hipStreamWaitEvent(J->stream, J->ev_join, 0);
-  if (e == hipSuccess) e = launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream, 2);
-  return e;
+  return launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->stream, 4);
+}
+
+// the U rows of block k on the second stream, after its contraction
+hipError_t do_urow_side(ifctn_job* J, const void* c) {
+  const int k = *(const int*)c;
+  return launch_gamma(J->gplan[k], J->dgp + k, J->flag + 1, J->side, 3);
 }
 
 hipError_t do_solve(ifctn_job* J, const void* c) {
@@ -1506,12 +1509,17 @@ hipError_t run_sweep(ifctn_job* J) {
       e = launch_stop_test(J->normpart, J->nnorm, J->stop_eps, J->flag + 1, J->stream);
     if (swap) {
       std::swap(J->stream, J->side);
+      // the U rows follow the contraction there; Gamma_k and the sum of its
+      // partial rows run here; the solve waits for both
+      if (e == hipSuccess) e = timed(J, KC_UROW, do_urow_side, &k);
       if (e == hipSuccess) e = hipEventRecord(J->ev_join, J->side);
       if (e == hipSuccess) e = timed(J, KC_GRAM, do_gamma_main, &k);
+      if (e == hipSuccess) e = timed(J, KC_UROW, do_gsum_main, &k);
+      if (e == hipSuccess) e = hipStreamWaitEvent(J->stream, J->ev_join, 0);
     }
     if (e != hipSuccess) return e;
-    if (J->groute[k]) {              // Gamma_k and the U rows, then the solve
-      e = swap ? timed(J, KC_UROW, do_urow_join, &k) : timed(J, KC_GRAM, do_gamma, &k);
+    if (J->groute[k] && !swap) {     // Gamma_k, the U rows and the partial-row sum, then the solve
+      e = timed(J, KC_GRAM, do_gamma, &k);
       if (e != hipSuccess) return e;
     }
     e = timed(J, KC_SOLVE, do_solve, &J->splan[k]);

@@ -461,7 +461,9 @@ bool kernel_events_used();
 hipError_t launch_solve(int dtype, const SolveArgs& a, hipStream_t s);
 // Gamma route: Gamma_k in a launch of its own (gm: device copy of hp), and the solve
 // part 1: Gamma_k (no dependence on X or U_k); part 2, after it and after the
-// contraction of block k: the U rows and the sum of Gamma_k's partial rows
+// contraction of block k: the U rows and the sum of Gamma_k's partial rows;
+// part 3: the U rows alone (after the contraction); part 4: the partial-row
+// sum alone (after Gamma_k)
 hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* stop, hipStream_t s, int part);
 hipError_t launch_solve_gamma(int dtype, const GSolve& hs, const GSolve* gs, hipStream_t s);
 size_t solve_smem_bytes(const SolveArgs& a);

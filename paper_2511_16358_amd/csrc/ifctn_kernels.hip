@@ -1154,8 +1154,8 @@ hipError_t launch_gamma(const GammaPlan& hp, const GammaPlan* gm, const int* sto
     const hipError_t e = allow_large_lds(k_gamma, hp.smem, &big);
     if (e != hipSuccess) return e;
   }
-  const int b0 = part == 2 ? hp.nw : 0;
-  const int nb = part == 1 ? hp.nw : hp.nuw + hp.nred;
+  const int b0 = part == 1 ? 0 : part == 4 ? hp.nw + hp.nuw : hp.nw;
+  const int nb = part == 1 ? hp.nw : part == 2 ? hp.nuw + hp.nred : part == 3 ? hp.nuw : hp.nred;
   if (nb <= 0) return hipSuccess;
   IFCTN_GO(k_gamma, dim3((unsigned)nb), dim3(NT), (size_t)hp.smem, s, gm, stop, b0);
   return hipGetLastError();
