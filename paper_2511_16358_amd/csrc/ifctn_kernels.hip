@@ -524,7 +524,9 @@ __global__ __launch_bounds__(NT) void k_solve_gamma(const GSolve* __restrict__ g
 
   // loads: Gamma_k and the far-side factors as one index space of segments
   // (a select over at most five segment bounds per element), the offset
-  // tables, the own-side columns and the U row, in wide batches
+  // tables, the own-side columns and the U row.  The first round of all four
+  // (16 + 8 + 1 + 1 per thread) is in flight together; longer arrays go on in
+  // further batches.
   {
     const int ntot = P + (gl ? gs->gik_tot : 0);
     long long sbase[MAXN - 1];
@@ -535,32 +537,69 @@ __global__ __launch_bounds__(NT) void k_solve_gamma(const GSolve* __restrict__ g
       sbeg[t] = t < n ? P + gs->gik_off[t] : ntot;
     }
     const double* gma = gs->gamma;
-    for_batched<16>(
-        ntot,
-        [&](int e) {
-          long long a = -1;
+    auto gsrc = [&](int e) {
+      long long a = -1;
 #pragma unroll
-          for (int t = 0; t < MAXN - 1; ++t)
-            if (e >= sbeg[t]) a = sbase[t] + (e - sbeg[t]);
-          const double* src = a < 0 ? gma + e : G + a;   // the address is selected, the load is not
-          return *src;
-        },
-        [&](int e, double v) { sm[e < P ? e : (int)(gik - sm) + (e - P)] = v; });
-  }
-  for_batched<8>(gs->tabtot, [&](int e) { return gs->tab[e]; }, [&](int e, int v) { tab[e] = v; });
-  for_batched<4>(
-      n * MAXR,
-      [&](int e) {
-        const int t = e / MAXR, r = e - t * MAXR;
-        return G[gs->goff_ki[t] + (long long)min(r, gs->R[t] - 1) * Ik + j];   // in bounds; padding zeroed below
-      },
-      [&](int e, double v) { g[e] = (e % MAXR) < gs->R[e / MAXR] ? v : 0.0; });
-  {
-    const long long stride = (long long)Ik * Rprod;
+      for (int t = 0; t < MAXN - 1; ++t)
+        if (e >= sbeg[t]) a = sbase[t] + (e - sbeg[t]);
+      return a < 0 ? gma + e : G + a;   // the address is selected, the load is not
+    };
+    auto gdst = [&](int e) { return e < P ? sm + e : gik + (e - P); };
+    const int tabtot = gs->tabtot, ng = n * MAXR;
+    auto gcol = [&](int e) {
+      const int t = e / MAXR, r = e - t * MAXR;
+      return G + gs->goff_ki[t] + (long long)min(r, gs->R[t] - 1) * Ik + j;   // in bounds; padding zeroed
+    };
+    const long long ustride = (long long)Ik * Rprod;
     const double* up = gs->Upart + (long long)j * Rprod;
-    for (int c = tid; c < Rprod; c += NT)
+    const bool u1 = gs->S == 1;           // U rows arrive reduced: one load per entry
+    double gv[16], cv, uv;
+    int tv[8];
+    // no chain tables (one other mode): read a valid word, never stored
+    const int* tsrc = tabtot > 0 ? gs->tab : (const int*)gs->gamma;
+#pragma unroll
+    for (int u = 0; u < 16; ++u) gv[u] = *gsrc(min(tid + u * NT, ntot - 1));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tv[u] = tsrc[min(tid + u * NT, max(tabtot - 1, 0))];
+    cv = *gcol(min(tid, ng - 1));
+    uv = up[min(tid, Rprod - 1)];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) gv[u] = pin(gv[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) tv[u] = pin(tv[u]);
+    cv = pin(cv);
+    uv = pin(uv);
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (tid + u * NT < ntot) *gdst(tid + u * NT) = gv[u];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (tid + u * NT < tabtot) tab[tid + u * NT] = tv[u];
+    if (tid < ng) g[tid] = (tid % MAXR) < gs->R[tid / MAXR] ? cv : 0.0;
+    if (u1 && tid < Rprod) urow[tid] = uv;
+    // the rest, in batches
+    for (int eb = tid + 16 * NT; eb < ntot; eb += 16 * NT) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) gv[u] = *gsrc(min(eb + u * NT, ntot - 1));
+#pragma unroll
+      for (int u = 0; u < 16; ++u) gv[u] = pin(gv[u]);
+#pragma unroll
+      for (int u = 0; u < 16; ++u)
+        if (eb + u * NT < ntot) *gdst(eb + u * NT) = gv[u];
+    }
+    for (int eb = tid + 8 * NT; eb < tabtot; eb += 8 * NT) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) tv[u] = gs->tab[min(eb + u * NT, tabtot - 1)];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) tv[u] = pin(tv[u]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        if (eb + u * NT < tabtot) tab[eb + u * NT] = tv[u];
+    }
+    for (int e = tid + NT; e < ng; e += NT) g[e] = (e % MAXR) < gs->R[e / MAXR] ? *gcol(e) : 0.0;
+    for (int c = u1 ? tid + NT : tid; c < Rprod; c += NT)
       urow[c] = ordered_sum<16>(
-          0.0, gs->S, [&](int q) { return up[(long long)q * stride + c]; }, [](int, double x) { return x; });
+          0.0, gs->S, [&](int q) { return up[(long long)q * ustride + c]; }, [](int, double x) { return x; });
   }
   for (int e = tid; e < n * MAXP; e += NT) {
     const int t = e / MAXP, p = e - t * MAXP;
