@@ -1,9 +1,9 @@
 """GPU parity of the large-rank route (jobs with an edge rank above 8, up to
 the rank grid's 36 of Sec. 5) against the FP64 oracle, through the C ABI:
 several sweeps in FP64 (1e-10) and FP32 (1e-5) on shapes of order 2-5 that
-span several GEMM tiles with ragged tails, ranks above the mode sizes, the
-and the stop rule of Algorithm 1 (the image rank grid up to 36 is served
-against the oracle in the serving tests)."""
+span several GEMM tiles with ragged tails and ranks above the mode sizes,
+run-to-run determinism, and the stop rule of Algorithm 1 (the image rank grid
+up to 36 is served against the oracle in the serving tests)."""
 import numpy as np
 import pytest
 
