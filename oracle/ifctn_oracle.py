@@ -18,7 +18,9 @@ Decomposition for Tensor Completion", arXiv 2511.16358):
   sub-problem (:func:`update_factor`), assembled literally per column j from
   D = diag(vec S_k), y_j and G_{i,k}.
 * eq. (updateX) -- the X step (:func:`update_x`).
-* Algorithm 1 -- initialisation, Gauss-Seidel order, stop rule (:func:`pam`).
+* Algorithm 1 -- initialisation, Gauss-Seidel order, stop rule (:func:`pam`);
+  its input G^0 drawn by a seeded default of the data's scale
+  (:func:`default_factors`, SplitMix64 of Steele, Lea and Flood 2014).
 * Sec. 5 -- RSE and RMSE (:func:`rse`, :func:`rmse`), MPSNR and MSSIM of
   image-shaped tensors (:func:`mpsnr`, :func:`mssim`; the standard
   definitions the paper cites, Wang et al. 2004 for SSIM).
@@ -276,6 +278,52 @@ def initial_x(O, mask):
     """X^0 = O on Omega and 0 elsewhere."""
     m = np.asarray(mask).astype(bool)
     return np.where(m, np.asarray(O, dtype=np.float64), 0.0)
+
+
+# --------------------------------------------------------------------------
+# A seeded default G^0 (Algorithm 1 takes G^0 as an input and leaves its
+# distribution open)
+# --------------------------------------------------------------------------
+def splitmix64(seed, n):
+    """Outputs n (an integer array) of SplitMix64 started from state `seed`
+    (Steele, Lea and Flood, "Fast splittable pseudorandom number generators",
+    OOPSLA 2014): the state advances by the odd constant 0x9E3779B97F4A7C15 per
+    output, so output n mixes seed + (n + 1) * 0x9E3779B97F4A7C15 (mod 2^64) by
+    z ^= z >> 30; z *= 0xBF58476D1CE4E5B9; z ^= z >> 27; z *= 0x94D049BB133111EB;
+    z ^= z >> 31 (all mod 2^64)."""
+    u64 = np.uint64
+    with np.errstate(over="ignore"):
+        z = u64(seed) + (np.asarray(n, dtype=u64) + u64(1)) * u64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> u64(30))) * u64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> u64(27))) * u64(0x94D049BB133111EB)
+        return z ^ (z >> u64(31))
+
+
+def default_factors(O, mask, dims, ranks, seed=0):
+    """Uniform initial factors with the scale of the data.  Entry n of the
+    factors taken in block order (k ascending, i ascending, each R_ki x I_k
+    row-major) is s * u_n, u_n = (SplitMix64 output n >> 11) / 2^53 in [0, 1).
+    Entries of mean s/2 make E[W_ab] = R_ab s^2 / 4 for every edge matrix, and
+    distinct edges use distinct factors, so E[Xhat] = prod_{a<b} R_ab s^2 / 4
+    (eq. (iFCTN)); s sets that to m, the root mean square of the observed
+    entries (m = 1 when none is observed or all are 0):
+    s = 2 (m / prod R_ab)^(1 / (2e)) over the e = N(N-1)/2 edges."""
+    N = len(dims)
+    vals = np.asarray(O, dtype=np.float64)[np.asarray(mask).astype(bool)]
+    m = float(np.sqrt(np.mean(vals * vals))) if vals.size else 0.0
+    if not (m > 0.0) or not np.isfinite(m):
+        m = 1.0
+    prod_r = 1.0
+    for a, b in edges(N):
+        prod_r *= ranks[a][b]
+    s = 2.0 * (m / prod_r) ** (1.0 / (2.0 * len(edges(N))))
+    G, n0 = {}, 0
+    for k, i in block_order(N):
+        cnt = int(ranks[k][i]) * int(dims[k])
+        u = (splitmix64(seed, np.arange(n0, n0 + cnt)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        G[(k, i)] = s * u.reshape(int(ranks[k][i]), int(dims[k]))
+        n0 += cnt
+    return G
 
 
 def pam(O, mask, G0, dims, rho=0.1, t_max=1000, eps=1e-5, rho_x=None, callback=None):

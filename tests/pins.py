@@ -521,10 +521,32 @@ def check_image_metrics(O):
     assert abs(O.mssim(Y, X) - np.mean([O.ssim_band(Y[:, :, b], X[:, :, b]) for b in range(3)])) < 1e-15
 
 
+def check_default_factors(O):
+    """The seeded default G^0: SplitMix64's published first outputs from state
+    0, entry n of the block order drawn from output n, and E[iFCTN(G^0)] = m,
+    the root mean square of the observed entries (averaged over 1000 seeds,
+    order 3, unequal ranks)."""
+    assert [int(v) for v in O.splitmix64(0, [0, 1, 2])] == [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4,
+                                                           0x06C45D188009454F]
+    rng = np.random.default_rng(11)
+    dims = (6, 5, 4)
+    R = sym_ranks(3, [2, 3, 4])
+    X = 5.0 * rng.random(dims)
+    mask = rng.random(dims) < 0.3
+    m = np.sqrt(np.mean(X[mask] ** 2))
+    G = O.default_factors(X, mask, dims, R, seed=5)
+    flat = np.concatenate([G[key].ravel() for key in O.block_order(3)])
+    s = 2.0 * (m / 24.0) ** (1.0 / 6.0)
+    for n in (0, flat.size - 1):
+        assert flat[n] == s * float(int(O.splitmix64(5, n)) >> 11) * 2.0 ** -53
+    means = [np.mean(O.reconstruct(O.default_factors(X, mask, dims, R, seed), dims)) for seed in range(1000)]
+    assert abs(np.mean(means) / m - 1.0) < 0.08
+
+
 ALL_CHECKS = [
     check_image_metrics,
     check_reconstruct_brute, check_n3_remark, check_cherry_kr, check_subnetwork,
     check_transposition, check_gauge, check_n2_ridge, check_block_probe, check_spd,
     check_x_update, check_sweep_replay, check_lemma2, check_stop_rule, check_fixed_point,
-    check_storage_count, check_observed_rows,
+    check_storage_count, check_observed_rows, check_default_factors,
 ]

@@ -239,6 +239,40 @@ def _mut_psnr_peak_not_squared(m):
     return "psnr_bands", psnr_bands
 
 
+def _default_factors_variant(m, scale, stat="rms", order=None):
+    def default_factors(O, mask, dims, ranks, seed=0):
+        N = len(dims)
+        vals = np.asarray(O, dtype=np.float64)[np.asarray(mask).astype(bool)]
+        mm = float(np.sqrt(np.mean(vals * vals)) if stat == "rms" else np.mean(vals)) if vals.size else 1.0
+        prod_r = float(np.prod([ranks[a][b] for a, b in m.edges(N)]))
+        s = scale(mm, prod_r, len(m.edges(N)))
+        G, n0 = {}, 0
+        for k, i in (order(N) if order else m.block_order(N)):
+            cnt = int(ranks[k][i]) * int(dims[k])
+            u = (m.splitmix64(seed, np.arange(n0, n0 + cnt)) >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+            G[(k, i)] = s * u.reshape(int(ranks[k][i]), int(dims[k]))
+            n0 += cnt
+        return G
+    return "default_factors", default_factors
+
+
+def _mut_default_scale_no_two(m):
+    return _default_factors_variant(m, lambda mm, p, e: (mm / p) ** (1.0 / (2 * e)))
+
+
+def _mut_default_exponent_per_edge(m):
+    return _default_factors_variant(m, lambda mm, p, e: 2.0 * (mm / p) ** (1.0 / e))
+
+
+def _mut_default_mean_not_rms(m):
+    return _default_factors_variant(m, lambda mm, p, e: 2.0 * (mm / p) ** (1.0 / (2 * e)), stat="mean")
+
+
+def _mut_default_i_major_order(m):
+    return _default_factors_variant(m, lambda mm, p, e: 2.0 * (mm / p) ** (1.0 / (2 * e)),
+                                    order=lambda N: [(k, i) for i in range(N) for k in range(N) if i != k])
+
+
 MUTATIONS = [
     _mut_reconstruct_drops_edge, _mut_edge_same_side, _mut_subnetwork_includes_k,
     _mut_y_includes_edge_ki, _mut_far_side_from_own, _mut_no_prox_in_b, _mut_no_prox_in_H,
@@ -247,6 +281,8 @@ MUTATIONS = [
     _mut_rel_uses_new_norm, _mut_rse_estimate_norm, _mut_rmse_all_entries,
     _mut_initial_x_keeps_unobserved, _mut_params_counts_edges_once, _mut_cholesky_upper_misuse,
     _mut_ssim_c2_not_squared, _mut_window_sigma, _mut_psnr_peak_not_squared,
+    _mut_default_scale_no_two, _mut_default_exponent_per_edge, _mut_default_mean_not_rms,
+    _mut_default_i_major_order,
 ]
 
 
