@@ -106,12 +106,27 @@ size_t ifctn_workspace_bytes(const ifctn_params* params);
  *   O_dev:    observed tensor, prod(dims) elements, float32 (FP32 and BF16_REFINE
  *             precision) or float64 (FP64 precision).  Entries off Omega are ignored.
  *   mask_dev: prod(dims) bytes, nonzero = observed (the sample set Omega).
- *   G0_host:  packed initial factors (float64), required (Algorithm 1 leaves
- *             G^0 to the caller).
+ *   G0_host:  packed initial factors (float64); NULL = the seeded default of
+ *             ifctn_default_factors with seed 0 (Algorithm 1 takes G^0 as an
+ *             input without fixing how it is drawn).
  * Fails with IFCTN_E_INVAL when an observed entry is not finite.  Synchronises
  * the stream.  On success *out owns all device memory until ifctn_destroy. */
 ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
                         const double* G0_host, void* stream, ifctn_job** out);
+
+/* Seeded default initial factors for Algorithm 1 (which takes G^0 as an
+ * input): writes ifctn_num_factor_entries(params) float64 values to G_host in
+ * the packed order.  Entry n is s * u_n, where u_n in [0, 1) is the top 53 bits
+ * of output n of SplitMix64 started from seed (the state after n + 1 steps,
+ * seed + (n + 1) * 0x9E3779B97F4A7C15, mixed as in Steele, Lea and Flood,
+ * OOPSLA 2014), and s = 2 (m / prod_{a<b} R_ab)^(1/(2e)) over the e = N(N-1)/2
+ * edges, so that the expected value of every entry of iFCTN(G^0) equals m, the
+ * root mean square of the observed entries of O (m = 1 when none is observed
+ * or all are 0; m is reduced on the device in a fixed order).  O_dev and
+ * mask_dev are as for ifctn_init.  Allocates a small device buffer and
+ * synchronises the stream.  IFCTN_E_INVAL for invalid params or NULL pointers. */
+ifctn_status ifctn_default_factors(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
+                                   uint64_t seed, void* stream, double* G_host);
 
 /* Run nsweeps >= 0 full PAM sweeps (every factor block by eq. (updateG), then
  * eq. (updateX)).  Asynchronous when stats is NULL; otherwise synchronises
@@ -137,7 +152,8 @@ ifctn_status ifctn_promote(ifctn_job* job);
 /* Release a job and its device memory (NULL is accepted). */
 ifctn_status ifctn_destroy(ifctn_job* job);
 
-/* Algorithm 1 end to end: init, sweeps until rel_change < eps or t_max sweeps
+/* Algorithm 1 end to end (G0_host as for ifctn_init: NULL = the seeded default
+ * of seed 0): init, sweeps until rel_change < eps or t_max sweeps
  * (eps = 0 runs exactly t_max), write X to X_out_dev (same dtype as O_dev),
  * fill *stats (nullable), destroy.  Synchronises.  BF16_REFINE: the first
  * t_max - refine_sweeps sweeps (or fewer, when the stop test is met) stream

@@ -1683,6 +1683,55 @@ ifctn_status ifctn_destroy(ifctn_job* job) {
 
 namespace ifctn {
 
+// Output n of SplitMix64 started from `seed` (Steele, Lea and Flood, "Fast
+// splittable pseudorandom number generators", OOPSLA 2014): the state after n + 1
+// steps is seed + (n + 1) gamma, mixed by two xor-shift-multiply rounds.
+uint64_t splitmix64(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + (n + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Seeded default G^0 (Algorithm 1 takes G^0 as an input and the paper draws
+// it without saying how): packed entry n is s u_n, u_n the 53 high bits of
+// SplitMix64 output n as a fraction in [0, 1).  With every factor entry of
+// mean s/2, E[W_ab] = R_ab s^2 / 4, and the edge matrices are built from
+// disjoint factors, so E[Xhat] = prod_{a<b} R_ab s^2 / 4; s is chosen to make
+// that the root mean square m of the observed entries (m = 1 when nothing is
+// observed or m is 0).  m is reduced on the device in a fixed order.
+ifctn_status default_factors(const Geo& g, const void* O_dev, const uint8_t* mask_dev, uint64_t seed,
+                             hipStream_t s, double* G) {
+  const int nb = (int)std::min<long long>(1024, std::max<long long>(1, (g.nX + NT - 1) / NT));
+  void* buf = nullptr;
+  HIPTRY(hipMalloc(&buf, (size_t)nb * 16));
+  double* part = (double*)buf;
+  unsigned long long* cnt = (unsigned long long*)(part + nb);
+  std::vector<double> hp(nb);
+  std::vector<unsigned long long> hc(nb);
+  hipError_t e = launch_obs_sumsq(g.dtype, O_dev, mask_dev, g.nX, part, cnt, nb, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, (size_t)nb * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), cnt, (size_t)nb * 8, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  HIPTRY(e);
+  double sum = 0.0;
+  unsigned long long c = 0;
+  for (int b = 0; b < nb; ++b) {
+    sum += hp[b];
+    c += hc[b];
+  }
+  double m = c > 0 ? std::sqrt(sum / (double)c) : 0.0;
+  if (!(m > 0.0) || !std::isfinite(m)) m = 1.0;
+  double prodR = 1.0;
+  for (int a = 0; a < g.N; ++a)
+    for (int b = a + 1; b < g.N; ++b) prodR *= g.R[a][b];
+  const double sc = 2.0 * std::pow(m / prodR, 1.0 / (2.0 * g.ne));
+  for (long long n = 0; n < g.nG; ++n)
+    G[n] = sc * ((double)(splitmix64(seed, (uint64_t)n) >> 11) * 0x1.0p-53);
+  return IFCTN_OK;
+}
+
 ifctn_status job_open(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
                       const double* G0_host, hipStream_t stream, unsigned char* pool, size_t pool_bytes,
                       bool check_now, const PlanOpts& opts, ifctn_job** out) {
@@ -1945,7 +1994,27 @@ extern "C" {
 
 ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
                         const double* G0_host, void* stream, ifctn_job** out) {
+  std::vector<double> G0;
+  if (!G0_host && params && O_dev && mask_dev) {   // the seeded default, seed 0
+    Geo g;
+    ifctn_status st = make_geo(params, &g);
+    if (st != IFCTN_OK) return st;
+    G0.resize((size_t)g.nG);
+    st = default_factors(g, O_dev, mask_dev, 0, (hipStream_t)stream, G0.data());
+    if (st != IFCTN_OK) return st;
+    G0_host = G0.data();
+  }
+  // job_open synchronises the stream before it returns, so G0 outlives the copy
   return job_open(params, O_dev, mask_dev, G0_host, (hipStream_t)stream, nullptr, 0, true, current_opts(), out);
+}
+
+ifctn_status ifctn_default_factors(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
+                                   uint64_t seed, void* stream, double* G_host) {
+  Geo g;
+  ifctn_status st = make_geo(params, &g);
+  if (st != IFCTN_OK) return st;
+  if (!O_dev || !mask_dev || !G_host) return fail(IFCTN_E_INVAL, "O_dev, mask_dev and G_host are required");
+  return default_factors(g, O_dev, mask_dev, seed, (hipStream_t)stream, G_host);
 }
 
 

@@ -441,6 +441,10 @@ enum KernelClass { KC_CONTRACT = 0, KC_SOLVE = 1, KC_UPDATE = 2, KC_GRAM = 3, KC
 // dtype: 0 = float32 streaming data, 1 = float64
 hipError_t launch_init_x(int dtype, const void* O, const uint8_t* mask, void* X, uint32_t* maskbits,
                          int* bad_flag, long long nX, hipStream_t s);
+// part[b], cnt[b]: sum of O^2 and count over the observed entries seen by
+// workgroup b of nblocks (grid-stride)
+hipError_t launch_obs_sumsq(int dtype, const void* O, const uint8_t* mask, long long nX, double* part,
+                           unsigned long long* cnt, int nblocks, hipStream_t s);
 // X_bf16 = bf16(X32) / out = observed ? X32 : float(X_bf16) (exact widening)
 hipError_t launch_narrow(const float* X32, bf16x* Xb, long long nX, hipStream_t s);
 hipError_t launch_widen(const bf16x* Xb, const uint32_t* maskbits, const float* X32, float* out, long long nX,

@@ -46,6 +46,41 @@ __global__ __launch_bounds__(NT) void k_init_x(const T* __restrict__ O, const ui
   if (lane == 0 && w0 + 1 < nw) bits[w0 + 1] = (uint32_t)(b >> 32);
 }
 
+// Sum of squares and count of the observed entries of O (the scale of the
+// seeded default factors): grid-stride over the tensor, one partial pair per
+// workgroup added in a fixed tree order, so the result does not depend on
+// timing.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_obs_sumsq(const T* __restrict__ O, const uint8_t* __restrict__ mask,
+                                                  long long nX, double* __restrict__ part,
+                                                  unsigned long long* __restrict__ cnt) {
+  __shared__ double ss[NT];
+  __shared__ unsigned long long sc[NT];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  unsigned long long c = 0;
+  for (long long L = (long long)blockIdx.x * NT + tid; L < nX; L += (long long)gridDim.x * NT)
+    if (mask[L]) {
+      const double v = (double)O[L];
+      s += v * v;
+      ++c;
+    }
+  ss[tid] = s;
+  sc[tid] = c;
+  __syncthreads();
+  for (int h = NT / 2; h > 0; h >>= 1) {
+    if (tid < h) {
+      ss[tid] += ss[tid + h];
+      sc[tid] += sc[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    part[blockIdx.x] = ss[0];
+    cnt[blockIdx.x] = sc[0];
+  }
+}
+
 // bf16 copy of X for the bf16 streaming phase, and its exact widening back
 // (observed entries taken from the float32 master, which holds O there)
 __global__ __launch_bounds__(NT) void k_narrow(const float* __restrict__ X32, bf16x* __restrict__ Xb, long long nX) {
@@ -1102,6 +1137,15 @@ hipError_t launch_init_x(int dtype, const void* O, const uint8_t* mask, void* X,
   else
     hipLaunchKernelGGL(k_init_x<double>, dim3(nblk(nX)), dim3(NT), 0, s, (const double*)O, mask,
                        (double*)X, bits, bad, nX);
+  return hipGetLastError();
+}
+
+hipError_t launch_obs_sumsq(int dtype, const void* O, const uint8_t* mask, long long nX, double* part,
+                           unsigned long long* cnt, int nblocks, hipStream_t s) {
+  if (dtype == 0)
+    hipLaunchKernelGGL(k_obs_sumsq<float>, dim3(nblocks), dim3(NT), 0, s, (const float*)O, mask, nX, part, cnt);
+  else
+    hipLaunchKernelGGL(k_obs_sumsq<double>, dim3(nblocks), dim3(NT), 0, s, (const double*)O, mask, nX, part, cnt);
   return hipGetLastError();
 }
 

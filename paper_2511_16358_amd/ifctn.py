@@ -34,7 +34,7 @@ EXPORTED = [
     "ifctn_assemble", "ifctn_timing_enable", "ifctn_timing_query", "ifctn_last_error",
     "ifctn_promote", "ifctn_server_create", "ifctn_server_submit", "ifctn_server_poll",
     "ifctn_server_queued", "ifctn_server_destroy", "ifctn_set_option", "ifctn_image_metrics",
-    "ifctn_plan_blocks", "ifctn_assemble_noalloc",
+    "ifctn_plan_blocks", "ifctn_assemble_noalloc", "ifctn_default_factors",
 ]
 
 
@@ -133,6 +133,7 @@ def lib():
         "ifctn_complete": (st, [P, vp, vp, dp, i32, ctypes.c_double, vp, S, vp]),
         "ifctn_assemble": (st, [P, dp, vp, vp]),
         "ifctn_assemble_noalloc": (st, [P, dp, vp, vp]),
+        "ifctn_default_factors": (st, [P, vp, vp, ctypes.c_uint64, vp, dp]),
         "ifctn_timing_enable": (st, [vp, i32]),
         "ifctn_timing_query": (st, [vp, i32, dp, ctypes.POINTER(ctypes.c_int64)]),
         "ifctn_last_error": (ctypes.c_char_p, []),
@@ -218,11 +219,16 @@ class Job:
         dt = _dtype(precision)
         self.O = torch.as_tensor(np.asarray(O)).to(device="cuda", dtype=dt).contiguous()
         self.mask = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to("cuda").contiguous()
-        g0 = G0 if isinstance(G0, np.ndarray) and G0.ndim == 1 else workloads.pack(G0, self.dims, self.ranks)
-        self._g0 = np.ascontiguousarray(g0, dtype=np.float64)
+        # G0 None: the library's seeded default (ifctn_default_factors, seed 0)
+        if G0 is None:
+            self._g0 = None
+        else:
+            g0 = G0 if isinstance(G0, np.ndarray) and G0.ndim == 1 else workloads.pack(G0, self.dims, self.ranks)
+            self._g0 = np.ascontiguousarray(g0, dtype=np.float64)
         h = ctypes.c_void_p()
         _check(lib().ifctn_init(ctypes.byref(self.params), ctypes.c_void_p(self.O.data_ptr()),
-                                ctypes.c_void_p(self.mask.data_ptr()), _dptr(self._g0),
+                                ctypes.c_void_p(self.mask.data_ptr()),
+                                None if self._g0 is None else _dptr(self._g0),
                                 _stream_handle(), ctypes.byref(h)))
         self.handle = h
 
@@ -285,14 +291,34 @@ def complete(O, mask, G0, dims, ranks, t_max, eps=0.0, rho=0.1, precision=IFCTN_
         Mt = mask.to(device="cuda", dtype=torch.uint8).contiguous()
     else:
         Mt = torch.as_tensor(np.asarray(mask, dtype=np.uint8)).to("cuda").contiguous()
-    g0 = np.ascontiguousarray(workloads.pack(G0, dims, ranks) if isinstance(G0, dict) else G0,
-                              dtype=np.float64)
+    g0 = None if G0 is None else np.ascontiguousarray(
+        workloads.pack(G0, dims, ranks) if isinstance(G0, dict) else G0, dtype=np.float64)
     out = torch.empty(dims, dtype=dt, device="cuda")
     s = IfctnStats()
     _check(lib().ifctn_complete(ctypes.byref(params), ctypes.c_void_p(Ot.data_ptr()),
-                                ctypes.c_void_p(Mt.data_ptr()), _dptr(g0), int(t_max), float(eps),
+                                ctypes.c_void_p(Mt.data_ptr()), None if g0 is None else _dptr(g0),
+                                int(t_max), float(eps),
                                 ctypes.c_void_p(out.data_ptr()), ctypes.byref(s), _stream_handle()))
     return out, s.as_dict()
+
+
+def default_factors(O, mask, dims, ranks, seed=0, precision=IFCTN_FP32, packed=False):
+    """The library's seeded default G^0 (ifctn_default_factors): uniform
+    entries scaled so that iFCTN(G^0) has the observed entries' root mean
+    square as its expected value.  A dict {(k, i): R_ki x I_k}, or the packed
+    float64 array with packed=True."""
+    dims = tuple(int(d) for d in dims)
+    params = make_params(dims, ranks, precision=precision)
+    dt = _dtype(precision)
+    Ot = torch.as_tensor(np.asarray(O) if not isinstance(O, torch.Tensor) else O).to(device="cuda", dtype=dt)
+    Ot = Ot.contiguous()
+    Mt = torch.as_tensor(np.asarray(mask, dtype=np.uint8) if not isinstance(mask, torch.Tensor) else mask)
+    Mt = Mt.to(device="cuda", dtype=torch.uint8).contiguous()
+    buf = np.empty(num_factor_entries(dims, ranks), dtype=np.float64)
+    _check(lib().ifctn_default_factors(ctypes.byref(params), ctypes.c_void_p(Ot.data_ptr()),
+                                       ctypes.c_void_p(Mt.data_ptr()), ctypes.c_uint64(int(seed)),
+                                       _stream_handle(), _dptr(buf)))
+    return buf if packed else workloads.unpack(buf, dims, ranks)
 
 
 def assemble(dims, ranks, G, precision=IFCTN_FP32, out=None, noalloc=False):
