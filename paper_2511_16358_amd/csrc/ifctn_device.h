@@ -240,6 +240,22 @@ __device__ __forceinline__ void for_batched(int n, Load load, Use use) {
       if (eb + u * NT < n) use(eb + u * NT, v[u]);
   }
 }
+
+// for_batched from element threadIdx.x + e0 on (e0 a multiple of NT): the rest
+// of an array whose first elements were loaded together with other arrays
+template <int U, typename Load, typename Use>
+__device__ __forceinline__ void for_batched_from(int e0, int n, Load load, Use use) {
+  for (int eb = threadIdx.x + e0; eb < n; eb += NT * U) {
+    decltype(load(0)) v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = load(min(eb + u * NT, n - 1));
+#pragma unroll
+    for (int u = 0; u < U; ++u) v[u] = pin(v[u]);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      if (eb + u * NT < n) use(eb + u * NT, v[u]);
+  }
+}
 // Grouped reduction of the partial slots (ContractArgs::ugrp): called by every
 // contraction workgroup after its partial slot is written.  The workgroup
 // releases its writes and counts itself in; the last of the group's

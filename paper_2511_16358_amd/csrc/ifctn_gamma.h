@@ -132,43 +132,87 @@ __device__ __forceinline__ void gamma_block(const GammaPlan* __restrict__ gp, in
   // prefix index of mode s (s < npre) for tuple q (row-major over the prefix modes)
   const int d1 = npre == 2 ? gp->dim[1] : 1;
   auto pidx = [&](int q, int s) { return s == 0 ? q / d1 : q % d1; };
-  if (n >= 2) {
-    const double* src = G + gp->goff[py];
-    for_batched<16>(gp->rank[py] * Ky, [&](int e) { return src[e]; }, [&](int e, double v) { gy[e] = v; });
-  }
   if (hasx) {
-    const double* src = G + gp->goff[px];
-    for_batched<16>(gp->rank[px] * Kx, [&](int e) { return src[e]; }, [&](int e, double v) { gx[e] = v; });
+    // the y and x factors, the squared x-y edge and the squared prefix edges
+    // towards y and x per tuple: the first round of all five (4 + 4 + 24 +
+    // 2 x 8 + 2 x 4 loads per thread) in flight together, the rest in batches
+    const double* srcy = G + gp->goff[py];
+    const double* srcx = G + gp->goff[px];
+    const int ny = gp->rank[py] * Ky, nx = gp->rank[px] * Kx, nxy = Kx * Ky, ncq = nqw * Ky, nwb = nqw * Kx;
     const EdgeRef exy = gp->e[px][py];
-    for_batched<16>(
-        Kx * Ky,
-        [&](int e) {
-          const int x = e / Ky, y = e - x * Ky;
-          return W64[exy.off + (long long)x * exy.s1 + (long long)y * exy.s2];
-        },
-        [&](int e, double v) { wa[e] = gm_sq(v); });
-    // squared prefix edges towards y and x, per tuple
     const EdgeRef e0y = gp->e[0][py], e1y = gp->e[npre == 2 ? 1 : 0][py];
-    for_batched<16>(
-        nqw * Ky,
-        [&](int e) {
-          const int qq = e / Ky, y = e - qq * Ky, q = qa + qq;
-          const double a = W64[e0y.off + (long long)pidx(q, 0) * e0y.s1 + (long long)y * e0y.s2];
-          const double b = npre == 2 ? W64[e1y.off + (long long)pidx(q, 1) * e1y.s1 + (long long)y * e1y.s2] : 1.0;
-          return gm_sq(a) * gm_sq(b);
-        },
-        [&](int e, double v) { cq[e] = v; });
     const EdgeRef e0x = gp->e[0][px], e1x = gp->e[npre == 2 ? 1 : 0][px];
-    for_batched<16>(
-        nqw * Kx,
-        [&](int e) {
-          const int qq = e / Kx, x = e - qq * Kx, q = qa + qq;
-          const double a = W64[e0x.off + (long long)pidx(q, 0) * e0x.s1 + (long long)x * e0x.s2];
-          const double b = npre == 2 ? W64[e1x.off + (long long)pidx(q, 1) * e1x.s1 + (long long)x * e1x.s2] : 1.0;
-          return gm_sq(a) * gm_sq(b);
-        },
+    const int s1 = npre == 2 ? 1 : 0;   // without a second prefix mode the b loads repeat the a address
+    auto axy = [&](int e) {
+      const int x = e / Ky, y = e - x * Ky;
+      return W64 + exy.off + (long long)x * exy.s1 + (long long)y * exy.s2;
+    };
+    auto acq = [&](int e, int s) {
+      const int qq = e / Ky, y = e - qq * Ky, q = qa + qq;
+      const EdgeRef& ed = s ? e1y : e0y;
+      return W64 + ed.off + (long long)pidx(q, s) * ed.s1 + (long long)y * ed.s2;
+    };
+    auto awb = [&](int e, int s) {
+      const int qq = e / Kx, x = e - qq * Kx, q = qa + qq;
+      const EdgeRef& ed = s ? e1x : e0x;
+      return W64 + ed.off + (long long)pidx(q, s) * ed.s1 + (long long)x * ed.s2;
+    };
+    double vy[4], vx[4], va[24], vq[8], vq2[8], vb[4], vb2[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) vy[u] = srcy[min(tid + u * NT, ny - 1)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) vx[u] = srcx[min(tid + u * NT, nx - 1)];
+#pragma unroll
+    for (int u = 0; u < 24; ++u) va[u] = *axy(min(tid + u * NT, nxy - 1));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      vq[u] = *acq(min(tid + u * NT, ncq - 1), 0);
+      vq2[u] = *acq(min(tid + u * NT, ncq - 1), s1);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      vb[u] = *awb(min(tid + u * NT, nwb - 1), 0);
+      vb2[u] = *awb(min(tid + u * NT, nwb - 1), s1);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      vy[u] = pin(vy[u]);
+      vx[u] = pin(vx[u]);
+      vb[u] = pin(vb[u]);
+      vb2[u] = pin(vb2[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 24; ++u) va[u] = pin(va[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      vq[u] = pin(vq[u]);
+      vq2[u] = pin(vq2[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int e = tid + u * NT;
+      if (e < ny) gy[e] = vy[u];
+      if (e < nx) gx[e] = vx[u];
+      if (e < nwb) wb[e] = gm_sq(vb[u]) * (s1 ? gm_sq(vb2[u]) : 1.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 24; ++u)
+      if (tid + u * NT < nxy) wa[tid + u * NT] = gm_sq(va[u]);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (tid + u * NT < ncq) cq[tid + u * NT] = gm_sq(vq[u]) * (s1 ? gm_sq(vq2[u]) : 1.0);
+    for_batched_from<16>(4 * NT, ny, [&](int e) { return srcy[e]; }, [&](int e, double v) { gy[e] = v; });
+    for_batched_from<16>(4 * NT, nx, [&](int e) { return srcx[e]; }, [&](int e, double v) { gx[e] = v; });
+    for_batched_from<16>(24 * NT, nxy, [&](int e) { return *axy(e); }, [&](int e, double v) { wa[e] = gm_sq(v); });
+    for_batched_from<16>(
+        8 * NT, ncq, [&](int e) { return gm_sq(*acq(e, 0)) * (s1 ? gm_sq(*acq(e, 1)) : 1.0); },
+        [&](int e, double v) { cq[e] = v; });
+    for_batched_from<16>(
+        4 * NT, nwb, [&](int e) { return gm_sq(*awb(e, 0)) * (s1 ? gm_sq(*awb(e, 1)) : 1.0); },
         [&](int e, double v) { wb[e] = v; });
   } else if (n == 2) {
+    const double* src = G + gp->goff[py];
+    for_batched<16>(gp->rank[py] * Ky, [&](int e) { return src[e]; }, [&](int e, double v) { gy[e] = v; });
     const EdgeRef e0y = gp->e[0][py];
     for_batched<16>(
         nqw * Ky,
