@@ -368,8 +368,11 @@ class Server:
         Ot = torch.as_tensor(O).to(device="cuda", dtype=dt).contiguous()
         Mt = torch.as_tensor(np.asarray(mask, dtype=np.uint8) if isinstance(mask, np.ndarray) else mask)
         Mt = Mt.to(device="cuda", dtype=torch.uint8).contiguous()
-        g0 = np.ascontiguousarray(workloads.pack(G0, dims, ranks) if isinstance(G0, dict) else G0,
-                                  dtype=np.float64)
+        if G0 is None:   # the library's seeded default (seed 0), drawn now on the current stream
+            g0 = default_factors(Ot, Mt, dims, ranks, seed=0, precision=precision, packed=True)
+        else:
+            g0 = np.ascontiguousarray(workloads.pack(G0, dims, ranks) if isinstance(G0, dict) else G0,
+                                      dtype=np.float64)
         out = torch.empty(dims, dtype=dt, device="cuda")
         if tag is None:
             tag = self._next

@@ -94,3 +94,24 @@ def test_init_without_g0_uses_the_seeded_default():
     # ifctn_complete with G0 NULL runs the same iteration
     Xc, st = ifctn.complete(O64, p.mask, None, p.dims, p.ranks, t_max=3, precision=ifctn.IFCTN_FP64)
     assert np.array_equal(Xc.cpu().numpy(), X0) and st["sweeps_done"] == 3
+
+
+def test_served_request_without_g0_equals_complete():
+    """A served request with G0 None takes the same seeded default (drawn at
+    submit) and gives X and the statistics of ifctn_complete with G0 NULL,
+    bit for bit."""
+    from paper_2511_16358_amd import ifctn
+    p = W.random_problem((11, 9, 8, 5), ranks_of(4, {}, default=2), seed=8, keep=0.4)
+    Xc, st = ifctn.complete(p.O, p.mask, None, p.dims, p.ranks, t_max=9, precision=ifctn.IFCTN_FP32)
+    srv = ifctn.Server(hbm_budget_bytes=64 << 20, max_active=2, num_streams=2, sweeps_per_round=4)
+    srv.submit(p.O, p.mask, None, p.dims, p.ranks, 9, precision=ifctn.IFCTN_FP32, tag=1)
+    got = []
+    for _ in range(300):
+        got += srv.poll(8, wait_ms=100)
+        if got:
+            break
+    srv.close()
+    assert len(got) == 1 and got[0]["status"] == ifctn.IFCTN_OK
+    assert np.array_equal(got[0]["X"].cpu().numpy(), Xc.cpu().numpy())
+    for key in ("sweeps_done", "rel_change", "objective", "dx_norm2", "dg_norm2"):
+        assert got[0]["stats"][key] == st[key], key
