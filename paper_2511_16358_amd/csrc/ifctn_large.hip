@@ -297,6 +297,7 @@ __global__ __launch_bounds__(LS_NT) void k_lr_solve(LrSolveArgs a) {
   __shared__ double gl[MAXN][LR_MAXR];
   __shared__ double gold[LR_MAXR];
   __shared__ double vs[LR_MAXR];
+  __shared__ double dinv[LR_MAXR];       // 1 / L(c, c)
   __shared__ double red[LS_NT];
   const int lane = threadIdx.x;
   const int j = blockIdx.x;
@@ -377,30 +378,44 @@ __global__ __launch_bounds__(LS_NT) void k_lr_solve(LrSolveArgs a) {
     v += a.rho * gold[lane];
   }
   // Cholesky H = L L^T, left-looking, L over the lower triangle of Hs: at
-  // step c lane r >= c forms H(r, c) - sum_{q<c} L(r, q) L(c, q), lane c's value
-  // gives L(c, c).  One wave: its LDS accesses complete in issue order, so the
-  // column written at step c is what every lane reads at step c + 1.
+  // step c lane r >= c forms H(r, c) - sum_{q<c} L(r, q) L(c, q) (four partial
+  // sums over q mod 4, added in a fixed order: a quarter of the dependent
+  // chain), lane c's value gives L(c, c).  One wave: its LDS accesses complete
+  // in issue order, so the column written at step c is what every lane reads
+  // at step c + 1.
   for (int c = 0; c < R; ++c) {
     double t = 0.0;
     if (lane >= c && lane < R) {
-      t = Hs[lane][c];
-      for (int q = 0; q < c; ++q) t -= Hs[lane][q] * Hs[c][q];
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int q = 0;
+      for (; q + 4 <= c; q += 4) {
+        s0 += Hs[lane][q] * Hs[c][q];
+        s1 += Hs[lane][q + 1] * Hs[c][q + 1];
+        s2 += Hs[lane][q + 2] * Hs[c][q + 2];
+        s3 += Hs[lane][q + 3] * Hs[c][q + 3];
+      }
+      for (; q < c; ++q) s0 += Hs[lane][q] * Hs[c][q];
+      t = Hs[lane][c] - ((s0 + s1) + (s2 + s3));
     }
     const double d = sqrt(lane_bcast(t, c));
-    if (lane > c && lane < R) Hs[lane][c] = t * (1.0 / d);
-    if (lane == c) Hs[c][c] = d;
+    const double id = 1.0 / d;
+    if (lane > c && lane < R) Hs[lane][c] = t * id;
+    if (lane == c) {
+      Hs[c][c] = d;
+      dinv[c] = id;
+    }
   }
   // L y = b: y_c = v_c / L(c, c), then lanes r > c subtract L(r, c) y_c
   for (int c = 0; c < R; ++c) {
     const double lrc = lane > c && lane < R ? Hs[lane][c] : 0.0;
-    const double yc = lane_bcast(v, c) / Hs[c][c];
+    const double yc = lane_bcast(v, c) * dinv[c];
     if (lane == c) v = yc;
     if (lane > c) v -= lrc * yc;
   }
   // L^T g = y: g_c = v_c / L(c, c), then lanes r < c subtract L(c, r) g_c
   for (int c = R - 1; c >= 0; --c) {
     const double lcr = lane < c ? Hs[c][lane] : 0.0;
-    const double gc = lane_bcast(v, c) / Hs[c][c];
+    const double gc = lane_bcast(v, c) * dinv[c];
     if (lane == c) v = gc;
     if (lane < c) v -= lcr * gc;
   }
