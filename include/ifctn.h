@@ -123,8 +123,8 @@ ifctn_status ifctn_init(const ifctn_params* params, const void* O_dev, const uin
  * edges, so that the expected value of every entry of iFCTN(G^0) equals m, the
  * root mean square of the observed entries of O (m = 1 when none is observed
  * or all are 0; m is reduced on the device in a fixed order).  O_dev and
- * mask_dev are as for ifctn_init.  Allocates a small device buffer and
- * synchronises the stream.  IFCTN_E_INVAL for invalid params or NULL pointers. */
+ * mask_dev are as for ifctn_init.  Takes a small stream-ordered device buffer
+ * (hipMallocAsync / hipFreeAsync on stream) and synchronises the stream.  IFCTN_E_INVAL for invalid params or NULL pointers. */
 ifctn_status ifctn_default_factors(const ifctn_params* params, const void* O_dev, const uint8_t* mask_dev,
                                    uint64_t seed, void* stream, double* G_host);
 

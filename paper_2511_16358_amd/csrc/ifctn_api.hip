@@ -1703,8 +1703,10 @@ uint64_t splitmix64(uint64_t seed, uint64_t n) {
 ifctn_status default_factors(const Geo& g, const void* O_dev, const uint8_t* mask_dev, uint64_t seed,
                              hipStream_t s, double* G) {
   const int nb = (int)std::min<long long>(1024, std::max<long long>(1, (g.nX + NT - 1) / NT));
+  // a stream-ordered buffer: unlike hipFree, hipFreeAsync does not wait for
+  // the other streams of the device (jobs a server may be running meanwhile)
   void* buf = nullptr;
-  HIPTRY(hipMalloc(&buf, (size_t)nb * 16));
+  HIPTRY(hipMallocAsync(&buf, (size_t)nb * 16, s));
   double* part = (double*)buf;
   unsigned long long* cnt = (unsigned long long*)(part + nb);
   std::vector<double> hp(nb);
@@ -1712,8 +1714,9 @@ ifctn_status default_factors(const Geo& g, const void* O_dev, const uint8_t* mas
   hipError_t e = launch_obs_sumsq(g.dtype, O_dev, mask_dev, g.nX, part, cnt, nb, s);
   if (e == hipSuccess) e = hipMemcpyAsync(hp.data(), part, (size_t)nb * 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipMemcpyAsync(hc.data(), cnt, (size_t)nb * 8, hipMemcpyDeviceToHost, s);
+  const hipError_t ef = hipFreeAsync(buf, s);
+  if (e == hipSuccess) e = ef;
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  (void)hipFree(buf);
   HIPTRY(e);
   double sum = 0.0;
   unsigned long long c = 0;
