@@ -44,7 +44,7 @@ CASES = [
 ]
 
 
-@pytest.mark.parametrize("precision", [0, 2], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("precision", [0, 1, 2], ids=["fp32", "bf16_refine", "fp64"])
 @pytest.mark.parametrize("dims,ranks,keep", CASES, ids=["x".join(map(str, c[0])) for c in CASES])
 def test_default_factors_match_oracle(dims, ranks, keep, precision):
     from paper_2511_16358_amd import ifctn
